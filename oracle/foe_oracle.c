@@ -351,9 +351,11 @@ int ora_ipiano(const ora_params* p, const double* f, const double* bank, const d
       trial(x_cur, x_prev, g, f, n, p, alpha, xh, xn);
       for (long q = 0; q < n; ++q) d[q] = xn[q] - x_cur[q];
       Fn = ora_energy_F(xn, H, W, bank, theta, nf, p->model, p->boundary);
+      double Gn = ora_energy_G(xn, f, H, W, p->model, p->lam1, p->lam2);
       s1 = dot_rows(g, d, H, W);
       s2 = dot_rows(d, d, H, W);
       trials = 1;
+      if (!isfinite(Fn) || !isfinite(Gn) || !isfinite(s1) || !isfinite(s2)) { status = ORA_ENONFINITE; break; }
       accepted = 1;
     } else {
       L *= p->eta_down;
@@ -362,11 +364,13 @@ int ora_ipiano(const ora_params* p, const double* f, const double* bank, const d
         trial(x_cur, x_prev, g, f, n, p, alpha, xh, xn);
         for (long q = 0; q < n; ++q) d[q] = xn[q] - x_cur[q];
         Fn = ora_energy_F(xn, H, W, bank, theta, nf, p->model, p->boundary);
+        double Gn = ora_energy_G(xn, f, H, W, p->model, p->lam1, p->lam2);
         s1 = dot_rows(g, d, H, W);
         s2 = dot_rows(d, d, H, W);
         ++trials;
-        if (!isfinite(Fn) || !isfinite(s1) || !isfinite(s2)) { status = ORA_ENONFINITE; break; }
-        if (Fn <= Fx + s1 + 0.5 * L * s2) { accepted = 1; break; }
+        /* a non-finite trial energy fails the descent test: rejected like any other trial */
+        int finite = isfinite(Fn) && isfinite(Gn) && isfinite(s1) && isfinite(s2);
+        if (finite && Fn <= Fx + s1 + 0.5 * L * s2) { accepted = 1; break; }
         if (trials > p->max_backtracks) { status = ORA_ELINESEARCH; break; }
         L *= p->eta_up;
       }
