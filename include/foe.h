@@ -1,0 +1,163 @@
+/*
+ * foe.h -- C ABI of the MI355X (gfx950) FoE + iPiano despeckling library.
+ *
+ * The library minimises the FoE-regularised speckle energies of
+ * Chen, Feng, Ranftl, Qiao and Pock, "A higher-order MRF based variational
+ * model for multiplicative noise reduction":
+ *
+ *   E(u, f) = E_FoE(u) + D(u, f),  E_FoE(u) = sum_i theta_i sum_p rho((k_i * u)_p),
+ *   rho(x) = log(1 + x^2)                                   (Sec. II-A, eq. (FOEmodel))
+ *
+ * with iPiano, u+ = (I + a dG)^{-1}(u - a grad F(u) + b (u - u_prev))
+ * (Sec. II-C, eq. (fplusg)), for three data terms:
+ *   FOE_MODEL_COMBINED  eq. (newmodel), w = log u:
+ *                       G(w) = sum_p lam1/2 (2w + f^2 e^{-2w}) + lam2/2 (e^{2w} - 2 f^2 w)
+ *   FOE_MODEL_LOG       eq. (original): COMBINED with lam2 = 0
+ *   FOE_MODEL_IDIV      eq. (variant), in u: G(u) = lam1/2 sum_p (u^2 - 2 f^2 log u)
+ * grad_w F = sum_i theta_i W K_i^T rho'(K_i e^w), W = diag(e^w) for the log models and
+ * grad_u F = sum_i theta_i K_i^T rho'(K_i u) for IDIV (Sec. II-C).  The prox of the log
+ * models is solved by Newton's method (Sec. II-C, eq. (subproblem)); IDIV uses the
+ * closed form printed in Sec. II-C.
+ *
+ * Conventions
+ *   - Images are row-major float32 planes of height x width, pitch = width, in
+ *     device memory (d_ prefix) owned by the caller.  Host arrays have no prefix.
+ *   - K_i is a true 2-D convolution with a 7x7 filter (centre tap (3,3)) of the image
+ *     extended by 3 pixels with the boundary map (SYMMETRIC = half-sample reflection,
+ *     ZERO, PERIODIC); K_i^T is its exact adjoint.
+ *   - Every call returns a foe_status; nothing throws across the ABI; out-parameters
+ *     are left untouched on error.  foe_last_error() describes the last failure of
+ *     the calling thread.
+ *   - Work is enqueued on the solver's HIP stream.  Calls that return host values
+ *     (solve, eval_energy, step) synchronise that stream before returning.
+ *   - A solver allocates all of its device scratch in foe_create; no other call
+ *     allocates.  A solver must not be used from two host threads at once.
+ */
+#ifndef FOE_H
+#define FOE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FOE_ABI_VERSION 1
+#define FOE_MAX_FILTERS 64
+#define FOE_KSIZE 7
+#define FOE_STATS_COLS 8
+
+typedef enum foe_status {
+  FOE_OK = 0,
+  FOE_EINVAL = 1,       /* invalid argument or parameter (checked on the host) */
+  FOE_ENOMEM = 2,       /* device allocation failed */
+  FOE_EDEVICE = 3,      /* HIP runtime error */
+  FOE_ELINESEARCH = 4,  /* backtracking exceeded max_backtracks; state = last accepted iterate */
+  FOE_ENONFINITE = 5,   /* a reduction produced NaN/Inf */
+  FOE_EINPUT = 6        /* f (or the init image) has a non-finite or non-positive pixel */
+} foe_status;
+
+typedef enum foe_model { FOE_MODEL_COMBINED = 0, FOE_MODEL_LOG = 1, FOE_MODEL_IDIV = 2 } foe_model;
+typedef enum foe_boundary { FOE_BC_SYMMETRIC = 0, FOE_BC_ZERO = 1, FOE_BC_PERIODIC = 2 } foe_boundary;
+typedef enum foe_step_mode { FOE_STEP_BACKTRACK = 0, FOE_STEP_FIXED = 1 } foe_step_mode;
+typedef enum foe_precision { FOE_PREC_FP32 = 0, FOE_PREC_BF16 = 1 } foe_precision;
+typedef enum foe_engine { FOE_ENGINE_AUTO = 0, FOE_ENGINE_VALU = 1, FOE_ENGINE_MFMA = 2 } foe_engine;
+
+/* Solver parameters.  foe_default_params() fills every field. */
+typedef struct foe_params {
+  int32_t height, width;   /* >= 4 each */
+  int32_t num_filters;     /* 1 .. FOE_MAX_FILTERS (the paper uses 48, Fig. 1) */
+  int32_t ksize;           /* must be 7 */
+  int32_t model;           /* foe_model */
+  int32_t boundary;        /* foe_boundary */
+  int32_t precision;       /* foe_precision: arithmetic of the filter-bank contraction */
+  int32_t step_mode;       /* foe_step_mode */
+  int32_t looks;           /* L >= 1; selects the default (lam1, lam2) of Sec. III-B */
+  int32_t max_iters;       /* iterations of foe_solve, >= 0; also the stats capacity */
+  int32_t max_backtracks;  /* rejected trials allowed per iteration, >= 0 */
+  int32_t newton_iters;    /* log-model prox: at most this many Newton iterations per pixel (each
+                              pixel stops when converged), 1 .. 100 */
+  int32_t engine;          /* foe_engine: VALU direct convolution or MFMA implicit GEMM */
+  int32_t reserved;
+  double lambda1, lambda2; /* < 0 => the paper's value for `looks` (log models only) */
+  double beta;             /* inertia b in [0, 1) */
+  double alpha_fixed;      /* step a of FOE_STEP_FIXED, > 0 */
+  double L0;               /* initial Lipschitz estimate of the backtracking mode, > 0 */
+  double eta_up;           /* L <- eta_up L on a rejected trial, > 1 */
+  double eta_down;         /* L <- eta_down L at the start of each iteration, in (0, 1] */
+} foe_params;
+
+/* Per-call summary. */
+typedef struct foe_summary {
+  int32_t iters_done;      /* accepted iterations of this call */
+  int32_t total_trials;    /* trials of this call (accepted + rejected) */
+  double H, F, G;          /* energies at the final iterate */
+  double L, alpha;         /* last accepted Lipschitz estimate and step */
+} foe_summary;
+
+typedef struct foe_solver foe_solver;
+
+/* Fill p with defaults: 48 filters, 7x7, COMBINED, SYMMETRIC, FP32, backtracking,
+ * looks = 1, max_iters = 300, max_backtracks = 40, newton_iters = 30, lambdas from looks,
+ * beta = 0.8, L0 = 1, eta_up = 2, eta_down = 1.  height/width are set to 0 (caller sets them). */
+void foe_default_params(foe_params* p);
+
+/* Create a solver.  filters_host: [num_filters][7][7] float32 row-major (k_i[a][b]);
+ * weights_host: [num_filters] theta_i >= 0, finite.  Both are copied.  hip_stream may be
+ * NULL (the null stream).  Allocates 8 planes of height*width floats plus O(tiles) scratch.
+ * Errors: EINVAL (parameters), ENOMEM, EDEVICE. */
+foe_status foe_create(const foe_params* p, const float* filters_host, const float* weights_host, void* hip_stream,
+                      foe_solver** out);
+
+foe_status foe_destroy(foe_solver* s);
+
+/* Run max_iters iPiano iterations on the observed amplitude d_f (> 0, finite).
+ * d_init (nullable): initial amplitude u^0 > 0; NULL => u^0 = f.  The iteration starts at
+ * x^0 = x^{-1} = log u^0 (log models) or u^0 (IDIV).  d_u_out receives the amplitude
+ * u = e^{x^N} (log models) or x^N.  sum_host (nullable) receives the summary; stats_host
+ * (nullable, [max_iters][8] doubles) receives per accepted iteration
+ *   {F(x+), G(x+), L, alpha, trials, <grad F(x), d>, |d|^2, |x - x_prev|^2}, d = x+ - x.
+ * A trial whose energies are not finite is rejected by the backtracking test; in FIXED mode it
+ * ends the solve with ENONFINITE.
+ * Errors: ELINESEARCH / ENONFINITE (d_u_out holds the last accepted iterate), EINPUT. */
+foe_status foe_solve(foe_solver* s, const float* d_f, const float* d_init, float* d_u_out, foe_summary* sum_host,
+                     double* stats_host);
+
+/* Resumable form: the iPiano state (x^n, x^{n-1}, L) lives in caller buffers d_x_cur and
+ * d_x_prev (in the model's variable: w for the log models, u for IDIV) and *L_inout, and
+ * is advanced by `iters` iterations in place.  Running 2 x 150 iterations gives the same
+ * bits as one call of 300. */
+foe_status foe_solve_from(foe_solver* s, const float* d_f, float* d_x_cur, float* d_x_prev, double* L_inout,
+                          int32_t iters, foe_summary* sum_host, double* stats_host);
+
+/* Probes running the same kernels as the solve path. */
+/* d_grad = grad F(d_x). */
+foe_status foe_eval_gradient(foe_solver* s, const float* d_x, float* d_grad);
+/* F(d_x) and G(d_x; d_f) in double. */
+foe_status foe_eval_energy(foe_solver* s, const float* d_x, const float* d_f, double* F, double* G);
+/* d_out = prox_{tau G}(d_xhat) pixelwise (log models: the safeguarded Newton of the solve path). */
+foe_status foe_eval_prox(foe_solver* s, const float* d_xhat, const float* d_f, double tau, float* d_out);
+/* One trial step at a forced Lipschitz estimate L_forced (alpha = 1.9 (1 - beta) / L_forced, or
+ * alpha_fixed in FIXED mode): d_xnext = prox(x - alpha grad F(x) + beta (x - xprev));
+ * info_host (nullable, 4 doubles) = {F(x+), G(x+), <grad F(x), d>, |d|^2}. */
+foe_status foe_step(foe_solver* s, const float* d_f, const float* d_x, const float* d_xprev, double L_forced,
+                    float* d_xnext, double* info_host);
+
+/* Kernel time of the last foe_solve / foe_solve_from in milliseconds (HIP events on the
+ * solver stream around the iteration loop), and the number of fused trial launches. */
+foe_status foe_last_timing(foe_solver* s, double* ms, int32_t* trial_launches);
+
+/* Measurement probe: launch the fused trial kernel `reps` times on the solver stream at the
+ * state left by the last solve (the same trial is recomputed; nothing is accepted), each
+ * launch bracketed by its own pair of HIP events; *ms_mean receives the mean per-launch
+ * duration in milliseconds.  Requires a previous foe_solve / foe_solve_from. */
+foe_status foe_profile_trial(foe_solver* s, int32_t reps, double* ms_mean);
+
+const char* foe_status_str(foe_status st);
+const char* foe_last_error(void);
+int32_t foe_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FOE_H */

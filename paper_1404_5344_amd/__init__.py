@@ -1,0 +1,235 @@
+"""Python binding of the MI355X FoE + iPiano despeckling library (C ABI in include/foe.h).
+
+Argument marshalling only: every step of the method runs in the HIP library
+``_lib/libfoe.so``.  PyTorch supplies device memory and the HIP stream.  There
+is no CPU fallback: if the library is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libfoe.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ELINESEARCH, ENONFINITE, EINPUT = 0, 1, 2, 3, 4, 5, 6
+COMBINED, LOG, IDIV = 0, 1, 2
+SYMMETRIC, ZERO, PERIODIC = 0, 1, 2
+BACKTRACK, FIXED = 0, 1
+FP32, BF16 = 0, 1
+ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA = 0, 1, 2
+STATS_COLS = 8
+STATS_NAMES = ("F", "G", "L", "alpha", "trials", "s1", "s2", "m")
+
+
+class FoeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_str(status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "height", "width", "num_filters", "ksize", "model", "boundary", "precision", "step_mode", "looks",
+        "max_iters", "max_backtracks", "newton_iters", "engine", "reserved")] + \
+        [(n, ctypes.c_double) for n in ("lambda1", "lambda2", "beta", "alpha_fixed", "L0", "eta_up", "eta_down")]
+
+
+class Summary(ctypes.Structure):
+    _fields_ = [("iters_done", ctypes.c_int32), ("total_trials", ctypes.c_int32), ("H", ctypes.c_double),
+                ("F", ctypes.c_double), ("G", ctypes.c_double), ("L", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_VP = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_1404_5344_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.foe_default_params.argtypes = [ctypes.POINTER(Params)]
+    L.foe_default_params.restype = None
+    L.foe_create.argtypes = [ctypes.POINTER(Params), _VP, _VP, _VP, ctypes.POINTER(_VP)]
+    L.foe_destroy.argtypes = [_VP]
+    L.foe_solve.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(Summary), _DP]
+    L.foe_solve_from.argtypes = [_VP, _VP, _VP, _VP, _DP, ctypes.c_int32, ctypes.POINTER(Summary), _DP]
+    L.foe_eval_gradient.argtypes = [_VP, _VP, _VP]
+    L.foe_eval_energy.argtypes = [_VP, _VP, _VP, _DP, _DP]
+    L.foe_eval_prox.argtypes = [_VP, _VP, _VP, ctypes.c_double, _VP]
+    L.foe_step.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _DP]
+    L.foe_last_timing.argtypes = [_VP, _DP, ctypes.POINTER(ctypes.c_int32)]
+    L.foe_profile_trial.argtypes = [_VP, ctypes.c_int32, _DP]
+    L.foe_status_str.argtypes = [ctypes.c_int]
+    L.foe_status_str.restype = ctypes.c_char_p
+    L.foe_last_error.argtypes = []
+    L.foe_last_error.restype = ctypes.c_char_p
+    L.foe_abi_version.restype = ctypes.c_int32
+    for name in ("foe_create", "foe_destroy", "foe_solve", "foe_solve_from", "foe_eval_gradient", "foe_eval_energy",
+                 "foe_eval_prox", "foe_step", "foe_last_timing", "foe_profile_trial"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def status_str(st: int) -> str:
+    return lib.foe_status_str(int(st)).decode()
+
+
+def _check(st: int, allow=(OK,)):
+    if st not in allow:
+        raise FoeError(st, lib.foe_last_error().decode())
+    return st
+
+
+def default_params(height: int, width: int, **kw) -> Params:
+    p = Params()
+    lib.foe_default_params(ctypes.byref(p))
+    p.height, p.width = int(height), int(width)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, shape=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return _VP(t.data_ptr())
+
+
+@dataclass
+class SolveResult:
+    u: object            # torch tensor [H, W]
+    summary: dict
+    stats: np.ndarray    # [iters_done, 8]
+    status: int
+
+
+class Solver:
+    """One image size and filter bank; owns device scratch.  All tensors are float32 CUDA [H, W]."""
+
+    def __init__(self, params: Params, filters, weights, stream=None):
+        torch = _torch()
+        self.params = params
+        self.shape = (params.height, params.width)
+        k = np.ascontiguousarray(np.asarray(filters, dtype=np.float32).reshape(-1, 7, 7))
+        th = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).reshape(-1))
+        if k.shape[0] != params.num_filters or th.shape[0] != params.num_filters:
+            raise ValueError("filters/weights do not match num_filters")
+        self._k, self._th = k, th
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _VP()
+        _check(lib.foe_create(ctypes.byref(params), k.ctypes.data_as(_VP), th.ctypes.data_as(_VP),
+                              _VP(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib.foe_destroy(self._h)
+            self._h = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _sync_in(self):
+        # inputs produced on torch's current stream must be complete before the solver stream reads them
+        torch = _torch()
+        if self.stream != torch.cuda.current_stream():
+            self.stream.wait_stream(torch.cuda.current_stream())
+
+    def solve(self, f, init=None, out=None, allow_failure=False) -> SolveResult:
+        torch = _torch()
+        self._sync_in()
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=f.device)
+        s = Summary()
+        stats = np.zeros((max(self.params.max_iters, 1), STATS_COLS))
+        st = lib.foe_solve(self._h, _dev_ptr(f, self.shape, "f"),
+                           _dev_ptr(init, self.shape, "init") if init is not None else None,
+                           _dev_ptr(out, self.shape, "out"), ctypes.byref(s), stats.ctypes.data_as(_DP))
+        _check(st, (OK, ELINESEARCH, ENONFINITE) if allow_failure else (OK,))
+        return SolveResult(out, s.as_dict(), stats[:s.iters_done].copy(), st)
+
+    def solve_from(self, f, x_cur, x_prev, L: float, iters: int, allow_failure=False):
+        """Advance the state (x_cur, x_prev, L) in place by `iters` iterations; returns (L, summary, stats)."""
+        self._sync_in()
+        Lc = ctypes.c_double(L)
+        s = Summary()
+        stats = np.zeros((max(iters, 1), STATS_COLS))
+        st = lib.foe_solve_from(self._h, _dev_ptr(f, self.shape, "f"), _dev_ptr(x_cur, self.shape, "x_cur"),
+                                _dev_ptr(x_prev, self.shape, "x_prev"), ctypes.byref(Lc), int(iters), ctypes.byref(s),
+                                stats.ctypes.data_as(_DP))
+        _check(st, (OK, ELINESEARCH, ENONFINITE) if allow_failure else (OK,))
+        return Lc.value, s.as_dict(), stats[:s.iters_done].copy()
+
+    def eval_gradient(self, x):
+        torch = _torch()
+        self._sync_in()
+        g = torch.empty(self.shape, dtype=torch.float32, device=x.device)
+        _check(lib.foe_eval_gradient(self._h, _dev_ptr(x, self.shape, "x"), _dev_ptr(g)))
+        return g
+
+    def eval_energy(self, x, f):
+        self._sync_in()
+        F, G = ctypes.c_double(), ctypes.c_double()
+        _check(lib.foe_eval_energy(self._h, _dev_ptr(x, self.shape, "x"), _dev_ptr(f, self.shape, "f"),
+                                   ctypes.byref(F), ctypes.byref(G)))
+        return F.value, G.value
+
+    def eval_prox(self, xhat, f, tau: float):
+        torch = _torch()
+        self._sync_in()
+        out = torch.empty(self.shape, dtype=torch.float32, device=xhat.device)
+        _check(lib.foe_eval_prox(self._h, _dev_ptr(xhat, self.shape, "xhat"), _dev_ptr(f, self.shape, "f"),
+                                 float(tau), _dev_ptr(out)))
+        return out
+
+    def step(self, f, x, xprev, L: float):
+        torch = _torch()
+        self._sync_in()
+        out = torch.empty(self.shape, dtype=torch.float32, device=x.device)
+        info = np.zeros(4)
+        _check(lib.foe_step(self._h, _dev_ptr(f, self.shape, "f"), _dev_ptr(x, self.shape, "x"),
+                            _dev_ptr(xprev, self.shape, "xprev"), float(L), _dev_ptr(out), info.ctypes.data_as(_DP)))
+        return out, dict(F=info[0], G=info[1], s1=info[2], s2=info[3])
+
+    def profile_trial(self, reps: int = 20) -> float:
+        """Mean duration (ms) of one fused trial launch, from per-launch HIP event pairs."""
+        ms = ctypes.c_double()
+        _check(lib.foe_profile_trial(self._h, int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def last_timing(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int32()
+        _check(lib.foe_last_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

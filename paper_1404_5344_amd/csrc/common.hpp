@@ -1,0 +1,50 @@
+// Shared host/device definitions of the FoE + iPiano library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace foe {
+
+constexpr int KS = 7;           // filter size
+constexpr int KK = KS * KS;     // taps per filter
+constexpr int R = 3;            // filter radius
+constexpr int MAX_NF = 64;
+constexpr int PART_COLS = 8;    // per-block partial sums: F, G, s1, s2, m, (unused) x3
+constexpr int STAT_COLS = 8;
+
+enum Model { COMBINED = 0, LOG = 1, IDIV = 2 };
+enum Boundary { SYMMETRIC = 0, ZERO = 1, PERIODIC = 2 };
+enum StepMode { BACKTRACK = 0, FIXED = 1 };
+enum Status { ST_OK = 0, ST_ELINESEARCH = 4, ST_ENONFINITE = 5, ST_EINPUT = 6 };
+
+// iPiano state kept in device memory; written only by the single-block decide kernel
+// and by the host before a launch sequence.
+struct DevState {
+  double L;            // current Lipschitz estimate (of the trial being run)
+  double alpha;        // current step
+  double Fcur;         // F(x^n)
+  double L_acc;        // L of the last accepted trial
+  double sums[PART_COLS];  // totals of the last reduction
+  int icur, iprev, icand;  // x ring indices: x^n, x^{n-1}, candidate
+  int gcur, gcand;         // gradient ring indices: grad F(x^n), candidate grad F(x+)
+  int iter;                // accepted iterations of this launch sequence
+  int target;              // iterations requested
+  int trials;              // trials of the current iteration so far
+  int total_trials;
+  int status;              // Status
+  int done;                // 1 => every later trial / decide launch is a no-op
+  int input_bad;           // set by the init kernel when f or u0 is invalid
+  int pad_;
+};
+
+// Solver-wide constants of one image.
+struct Problem {
+  int H, W;
+  int nf;
+  int model, bc, step_mode;
+  int max_backtracks, newton_iters;
+  float lam1, lam2, beta;
+  double beta_d, eta_up, eta_down, alpha_fixed;
+};
+
+}  // namespace foe

@@ -1,0 +1,86 @@
+// Pointwise device functions of the FoE + iPiano path: boundary map, data terms, prox.
+#pragma once
+#include "common.hpp"
+
+namespace foe {
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// e^x through the hardware 2^x
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+// ln x through the hardware log2
+__device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+
+// Read-only data addressed through the constant address space: wave-uniform loads from it
+// become scalar loads (filter taps and weights live in SGPRs, not VGPRs).
+typedef const __attribute__((address_space(4))) float cfloat;
+__device__ __forceinline__ cfloat* as_const(const float* p) { return (cfloat*)p; }
+
+// Ring-buffer selection by a state index without indexing the kernel-argument block.
+__device__ __forceinline__ float* pick3(int i, float* a, float* b, float* c) { return i == 0 ? a : (i == 1 ? b : c); }
+__device__ __forceinline__ float* pick2(int i, float* a, float* b) { return i == 0 ? a : b; }
+
+// Boundary map of the 3-pixel extension: extended index q -> source pixel, or -1 where the
+// extension is zero or the sample is never read (SYMMETRIC beyond 3 pixels).
+__device__ __forceinline__ int bmap(int q, int n, int bc) {
+  if ((unsigned)q < (unsigned)n) return q;
+  if (bc == PERIODIC) {
+    int r = q % n;
+    return r < 0 ? r + n : r;
+  }
+  if (bc == SYMMETRIC && q >= -R && q < n + R) return q < 0 ? -1 - q : 2 * n - 1 - q;
+  return -1;
+}
+
+// Per-pixel data term G_p(x; f) of the three models; u = e^x for the log models, u = x for IDIV.
+__device__ __forceinline__ float data_term(float x, float u, float f, int model, float lam1, float lam2) {
+  float f2 = f * f;
+  if (model == IDIV) return 0.5f * lam1 * (x * x - 2.0f * f2 * fast_log(x));
+  float iu = fast_rcp(u);
+  float t = 0.5f * lam1 * (2.0f * x + f2 * iu * iu);
+  if (model == COMBINED) t += 0.5f * lam2 * (u * u - 2.0f * f2 * x);
+  return t;
+}
+
+// prox_{tau G}(xh) at one pixel.
+// Log models: the root of phi(w) = w - xh + tau lam1 (1 - f^2 e^{-2w}) + tau lam2 (e^{2w} - f^2),
+// solved for t = w - log f (so f^2 e^{-2w} = e^{-2t}): Newton's method from t = xh - log f, kept
+// inside the bracket [min(t_hat, 0), max(t_hat, 0)] that holds the root (both data terms are
+// minimised at w = log f, and phi is increasing); a step that leaves the bracket or is not
+// finite is replaced by bisection.  Each pixel stops at |dt| <= 4e-7 max(1, |w|) or after
+// max_iters iterations; the loop ends when every pixel of the wavefront has stopped.  A
+// pixel's result depends only on its own inputs.
+// IDIV: the positive root of (1 + tau lam) u^2 - xh u - tau lam f^2 = 0, in the form
+// without cancellation for xh < 0.
+__device__ __forceinline__ float prox_pixel(float xh, float f, float tau, int model, float lam1, float lam2,
+                                            int max_iters) {
+  if (model == IDIV) {
+    float a = 1.0f + tau * lam1;
+    float c = tau * lam1 * f * f;
+    float s = sqrtf(xh * xh + 4.0f * a * c);
+    return xh >= 0.0f ? (xh + s) * fast_rcp(2.0f * a) : 2.0f * c * fast_rcp(s - xh);
+  }
+  const float a1 = tau * lam1;
+  const float b2 = (model == COMBINED) ? tau * lam2 * f * f : 0.0f;
+  const float lf = fast_log(f);
+  const float th = xh - lf;
+  float lo = fminf(th, 0.0f), hi = fmaxf(th, 0.0f);
+  float t = th;
+  bool done = false;
+  for (int it = 0; it < max_iters; ++it) {
+    if (!done) {
+      float e = fast_exp(2.0f * t);          // e^{2t}
+      float em = fast_rcp(e);                // e^{-2t}
+      float phi = (t - th) + a1 * (1.0f - em) + b2 * (e - 1.0f);
+      float dphi = 1.0f + 2.0f * a1 * em + 2.0f * b2 * e;
+      if (phi > 0.0f) hi = fminf(hi, t); else if (phi < 0.0f) lo = fmaxf(lo, t);
+      float tn = t - phi * fast_rcp(dphi);
+      if (!(tn >= lo && tn <= hi)) tn = 0.5f * (lo + hi);
+      done = fabsf(tn - t) <= 4e-7f * fmaxf(1.0f, fabsf(tn + lf)) || phi == 0.0f;
+      t = tn;
+    }
+    if (__all(done)) break;
+  }
+  return t + lf;
+}
+
+}  // namespace foe

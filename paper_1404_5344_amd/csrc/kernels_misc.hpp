@@ -1,0 +1,138 @@
+// Small kernels of the iPiano loop: initial state, line-search decision, output, prox probe.
+#pragma once
+#include "device_math.hpp"
+
+namespace foe {
+
+// x^0 = x^{-1} = log u0 (log models) or u0 (IDIV), u0 = init or f.  Flags invalid input.
+__global__ void init_state_kernel(const float* __restrict__ f, const float* __restrict__ u0, float* x0, float* x1,
+                                  size_t n, int model, DevState* st) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    float fv = f[i];
+    float uv = u0 ? u0[i] : fv;
+    bad |= !(fv > 0.0f && fv <= 3.0e38f) || !(uv > 0.0f && uv <= 3.0e38f);
+    float x = model == IDIV ? uv : logf(uv);
+    x0[i] = x;
+    x1[i] = x;
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->input_bad, 1);
+}
+
+// Validity check of caller-provided state (resumable entry point).
+__global__ void check_input_kernel(const float* __restrict__ f, size_t n, DevState* st) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    float fv = f[i];
+    bad |= !(fv > 0.0f && fv <= 3.0e38f);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->input_bad, 1);
+}
+
+enum DecideMode { DECIDE_STEP = 0, DECIDE_INIT = 1, DECIDE_REPORT = 2 };
+
+// Single-block reduction of the per-block partials in a fixed order, then (DECIDE_STEP) the
+// backtracking test: accept iff F(x+) <= F(x) + <grad F(x), d> + L/2 |d|^2 (descent lemma), which a
+// non-finite F(x+) or G(x+) fails;
+// on acceptance rotate the x and gradient rings and record the stats row; on rejection
+// L <- eta_up L.  FIXED mode always accepts.
+__global__ __launch_bounds__(256) void decide_kernel(DevState* st, const double* __restrict__ partials, int nblocks,
+                                                     Problem pb, double* stats, int mode) {
+  if (mode == DECIDE_STEP && st->done) return;
+  __shared__ double red[256 / 64][5];
+  double v[5] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] += partials[(size_t)b * PART_COLS + k];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) red[wave][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double tot[5];
+  for (int k = 0; k < 5; ++k) tot[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+  for (int k = 0; k < 5; ++k) st->sums[k] = tot[k];
+  if (mode == DECIDE_REPORT) return;
+  if (mode == DECIDE_INIT) {
+    st->Fcur = tot[0];
+    if (st->input_bad) {
+      st->status = ST_EINPUT;
+      st->done = 1;
+    } else if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+      st->status = ST_ENONFINITE;
+      st->done = 1;
+    }
+    if (st->target <= 0) st->done = 1;
+    return;
+  }
+  const double F = tot[0], G = tot[1], s1 = tot[2], s2 = tot[3], m = tot[4];
+  st->trials += 1;
+  st->total_trials += 1;
+  const bool finite = isfinite(F) && isfinite(G) && isfinite(s1) && isfinite(s2);
+  if (!finite && pb.step_mode == FIXED) {
+    st->status = ST_ENONFINITE;
+    st->done = 1;
+    return;
+  }
+  const double L = st->L;
+  // a trial with a non-finite energy fails the descent test and is rejected like any other
+  const bool accept = finite && (pb.step_mode == FIXED || F <= st->Fcur + s1 + 0.5 * L * s2);
+  if (accept) {
+    double* row = stats + (size_t)st->iter * STAT_COLS;
+    row[0] = F; row[1] = G; row[2] = L; row[3] = st->alpha;
+    row[4] = (double)st->trials; row[5] = s1; row[6] = s2; row[7] = m;
+    const int c = st->icur, p = st->iprev, n = st->icand;
+    st->icur = n; st->iprev = c; st->icand = p;
+    const int g = st->gcur;
+    st->gcur = st->gcand; st->gcand = g;
+    st->Fcur = F;
+    st->L_acc = L;
+    st->iter += 1;
+    st->trials = 0;
+    if (st->iter >= st->target) st->done = 1;
+    if (pb.step_mode == BACKTRACK) {
+      st->L = pb.eta_down * L;
+      st->alpha = 1.9 * (1.0 - pb.beta_d) / st->L;
+    }
+  } else if (st->trials > pb.max_backtracks) {
+    st->status = ST_ELINESEARCH;
+    st->done = 1;
+  } else {
+    st->L = pb.eta_up * L;
+    st->alpha = 1.9 * (1.0 - pb.beta_d) / st->L;
+  }
+}
+
+// u = e^{x^n} (log models) or x^n, from the ring slot the state names.
+__global__ void finalize_kernel(const DevState* st, const float* x0, const float* x1, const float* x2, float* u,
+                                size_t n, int model) {
+  const float* x = pick3(st->icur, (float*)x0, (float*)x1, (float*)x2);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    u[i] = model == IDIV ? x[i] : expf(x[i]);
+}
+
+// Copy the ring slots the state names into caller buffers (resumable entry point).
+__global__ void export_state_kernel(const DevState* st, const float* x0, const float* x1, const float* x2,
+                                    float* xcur, float* xprev, size_t n) {
+  const float* c = pick3(st->icur, (float*)x0, (float*)x1, (float*)x2);
+  const float* p = pick3(st->iprev, (float*)x0, (float*)x1, (float*)x2);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    xcur[i] = c[i];
+    xprev[i] = p[i];
+  }
+}
+
+__global__ void prox_probe_kernel(const float* __restrict__ xh, const float* __restrict__ f, float* out, size_t n,
+                                  float tau, Problem pb) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = prox_pixel(xh[i], f[i], tau, pb.model, pb.lam1, pb.lam2, pb.newton_iters);
+}
+
+}  // namespace foe

@@ -1,0 +1,57 @@
+"""Write stored oracle results used by the GPU parity tests.
+
+Calls only the FP64 oracle (oracle/) and the seeded generators (synth/).  Run:
+    python tests/golden/make_golden.py [config2]
+Each output records the generator recipe, the model parameters and the oracle's
+per-iteration trajectory, so a test can compare without re-running a long oracle.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def config2(iters: int = 300):
+    pr = synth.config2()
+    bank = synth.dct_bank()
+    theta = synth.theta_weights(2)
+    p = oracle.Params(model=oracle.COMBINED, boundary=oracle.SYMMETRIC, lam1=pr.lam1, lam2=pr.lam2, beta=0.8)
+    t = time.time()
+    r = oracle.ipiano(p, pr.f, bank, theta, iters, L0=1.0)
+    dt = time.time() - t
+    u = r.u()
+    out = {
+        "what": "FP64 oracle, config 2: 512x512 shapes+cosine image, L = 1 speckle, COMBINED model, "
+                "SYMMETRIC boundary, DCT bank, theta seed 2, backtracking (L0 = 1, eta_up = 2, eta_down = 1), "
+                "beta = 0.8, 300 iterations",
+        "status": r.status,
+        "lam1": pr.lam1, "lam2": pr.lam2,
+        "psnr_noisy": synth.psnr(pr.f, pr.clean),
+        "psnr_final": synth.psnr(u, pr.clean),
+        "F": r.stats[:, 0].tolist(), "G": r.stats[:, 1].tolist(), "L": r.stats[:, 2].tolist(),
+        "trials": r.stats[:, 4].tolist(),
+        "u_sample_idx": list(range(0, 512 * 512, 4099)),
+        "u_sample": u.ravel()[::4099].tolist(),
+        "oracle_seconds": dt, "oracle_threads": oracle.get_threads(),
+    }
+    with open(os.path.join(HERE, "config2_oracle.json"), "w") as fh:
+        json.dump(out, fh)
+    print("config2: psnr", out["psnr_noisy"], "->", out["psnr_final"], "in", dt, "s")
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["config2"]
+    for w in which:
+        globals()[w]()

@@ -1,0 +1,119 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Bars (all float32 on the GPU against float64 on the CPU, same float32 inputs):
+  * gradient probe:  |g_gpu - g_ora|_inf / |g_ora|_inf <= 1e-4
+  * energies:        relative 2e-6 (F), 1e-6 (G)
+  * prox probe:      |x_gpu - x_ora| <= 1e-5 max(1, |x_ora|) elementwise
+  * one trial step at a forced L (teacher-forced): |x+_gpu - x+_ora|_inf / |x+_ora|_inf <= 1e-5
+Sizes span one to many 32x32 tiles with ragged tails; the three models and three boundary maps.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import bank_and_theta, make_solver, oracle_params, rel_inf, speckled, state_for, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+MODELS = [oracle.COMBINED, oracle.LOG, oracle.IDIV]
+BCS = [oracle.SYMMETRIC, oracle.ZERO, oracle.PERIODIC]
+SIZES = [(8, 8), (13, 21), (37, 64), (70, 45), (100, 131)]
+LAMS = {oracle.COMBINED: (358.0, 0.0104), oracle.LOG: (358.0, 0.0), oracle.IDIV: (10.0, 0.0)}
+
+
+def _gpu(t, dev):
+    torch, _ = torch_dev()
+    return torch.from_numpy(np.ascontiguousarray(t, dtype=np.float32)).to(dev)
+
+
+@pytest.mark.parametrize("model", MODELS)
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", SIZES)
+def test_gradient_and_energy(model, bc, shape):
+    torch, dev = torch_dev()
+    H, W = shape
+    clean, f = speckled(H, W, seed=H * 1000 + W)
+    bank, theta = bank_and_theta("random" if (H + W + bc) % 2 else "dct", seed=H + W)
+    x = state_for(model, f)
+    l1, l2 = LAMS[model]
+    s = make_solver(H, W, bank, theta, model=model, boundary=bc, lambda1=l1, lambda2=l2)
+    g = s.eval_gradient(_gpu(x, dev)).cpu().numpy()
+    g_ora = oracle.grad_F(x, bank, theta, model, bc)
+    assert rel_inf(g, g_ora) <= 1e-4, (model, bc, shape, rel_inf(g, g_ora))
+    F, G = s.eval_energy(_gpu(x, dev), _gpu(f, dev))
+    F_ora = oracle.energy_F(x, bank, theta, model, bc)
+    G_ora = oracle.energy_G(x, f, model, l1, l2)
+    assert abs(F - F_ora) <= 2e-6 * abs(F_ora), (F, F_ora)
+    assert abs(G - G_ora) <= 1e-6 * abs(G_ora) + 1e-6, (G, G_ora)
+    s.close()
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_prox(model):
+    torch, dev = torch_dev()
+    H, W = 64, 96
+    clean, f = speckled(H, W, looks=1, seed=5)
+    r = np.random.default_rng(0)
+    l1, l2 = LAMS[model]
+    bank, theta = bank_and_theta("dct")
+    s = make_solver(H, W, bank, theta, model=model, lambda1=l1, lambda2=l2)
+    for tau in (1e-6, 3e-5, 1e-3, 0.05):
+        if model == oracle.IDIV:
+            xh = (f + r.uniform(-100, 100, f.shape)).astype(np.float32)
+        else:
+            xh = (np.log(f) + r.uniform(-3, 3, f.shape)).astype(np.float32)
+        out = s.eval_prox(_gpu(xh, dev), _gpu(f, dev), tau).cpu().numpy()
+        ref = oracle.prox(xh, f, float(np.float32(tau)), model, l1, l2)
+        err = np.abs(out - ref) / np.maximum(1.0, np.abs(ref))
+        assert err.max() <= 1e-5, (tau, err.max())
+    s.close()
+
+
+@pytest.mark.parametrize("model", MODELS)
+@pytest.mark.parametrize("bc", BCS)
+def test_step_teacher_forced(model, bc):
+    torch, dev = torch_dev()
+    H, W = 70, 45
+    clean, f = speckled(H, W, looks=4, seed=11)
+    bank, theta = bank_and_theta("dct")
+    l1, l2 = LAMS[model]
+    po = oracle_params(model, bc, l1, l2)
+    # reach a mid-run state with the oracle, then compare one step at the oracle's accepted L
+    res = oracle.ipiano(po, f, bank, theta, 6, L0=1.0)
+    assert res.status == oracle.OK
+    x = res.x.astype(np.float32)
+    xp = res.x_prev.astype(np.float32)
+    L = float(res.L)
+    s = make_solver(H, W, bank, theta, model=model, boundary=bc, lambda1=l1, lambda2=l2)
+    xn, info = s.step(_gpu(f, dev), _gpu(x, dev), _gpu(xp, dev), L)
+    xn = xn.cpu().numpy()
+    xn_ora, info_ora = oracle.step(po, f, bank, theta, x, xp, L)
+    assert rel_inf(xn, xn_ora) <= 1e-5, rel_inf(xn, xn_ora)
+    d_gpu = xn - x
+    d_ora = xn_ora - x
+    # increment error, reported separately; float32 storage of x+ bounds it below by a few ulp of x
+    inc_err = float(np.max(np.abs(d_gpu - d_ora)))
+    print(f"step model {model} bc {bc}: |x+ err| rel {rel_inf(xn, xn_ora):.2e}, |d err| {inc_err:.2e} "
+          f"vs |d| {np.max(np.abs(d_ora)):.2e}")
+    assert inc_err <= 2e-3 * np.max(np.abs(d_ora)) + 8 * np.finfo(np.float32).eps * np.max(np.abs(x))
+    assert abs(info["F"] - info_ora["F"]) <= 2e-6 * abs(info_ora["F"])
+    # |d|^2: the device reduction equals the sum over the returned float32 x+, and matches the oracle
+    # up to the float32 storage of x+ (sqrt(N) ulp of x)
+    assert abs(info["s2"] - float(np.sum(d_gpu.astype(np.float64) ** 2))) <= 1e-6 * info["s2"]
+    q = np.sqrt(d_gpu.size) * 8 * np.finfo(np.float32).eps * np.max(np.abs(x))
+    assert abs(np.sqrt(info["s2"]) - np.sqrt(info_ora["s2"])) <= 2e-3 * np.sqrt(info_ora["s2"]) + q
+    s.close()
+
+
+def test_random_filters_and_fewer_filters():
+    """Nothing may rely on the DCT bank: random non-separable filters, 13 filters (ragged chunk)."""
+    torch, dev = torch_dev()
+    H, W = 45, 77
+    clean, f = speckled(H, W, seed=3)
+    bank, theta = bank_and_theta("random", nf=13, seed=7)
+    x = state_for(oracle.COMBINED, f)
+    s = make_solver(H, W, bank, theta)
+    g = s.eval_gradient(_gpu(x, dev)).cpu().numpy()
+    assert rel_inf(g, oracle.grad_F(x, bank, theta)) <= 1e-4
+    s.close()
