@@ -39,7 +39,7 @@ foe_status fail(foe_status st, const std::string& msg) {
   } while (0)
 
 // Default tile configuration of the VALU engine.
-constexpr int V_TW = 32, V_TH = 32, V_NC = 8, V_NT = 512, V_NG = 2;
+constexpr int V_TW = 32, V_TH = 32, V_NC = 16, V_NT = 512, V_BR = 4, V_BC = 2;
 constexpr int GRAPH_BIG = 16;
 
 // The paper's lambda1, lambda2 for L = 1, 3, 8 looks (Sec. III-B); other L are interpolated
@@ -103,7 +103,7 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
 }
 
 void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
-  fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_NG><<<s->nblocks, V_NT, 0, stream>>>(a);
+  fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC><<<s->nblocks, V_NT, 0, stream>>>(a);
 }
 
 void launch_decide(foe_solver* s, int mode, hipStream_t stream) {

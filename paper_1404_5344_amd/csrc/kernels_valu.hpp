@@ -56,8 +56,8 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* red, dou
   }
 }
 
-// Fold slots of the SYMMETRIC boundary map: the extended samples q != p with source p.
-// Slot layout (TW/TH = tile width/height):
+// Fold slots of the SYMMETRIC boundary map: the extended samples q != p with source p, for
+// pixels p within 3 of the image border.  Slot layout (TW/TH = tile width/height):
 //   [0, 3TW)            y-low   q = (-1-py, px),        py in [0,2]
 //   [3TW, 6TW)          y-high  q = (2H-1-py, px),      py in [H-3, H-1]
 //   [6TW, 6TW+3TH)      x-low   q = (py, -1-px),        px in [0,2]
@@ -101,23 +101,45 @@ __device__ __forceinline__ bool slot_target(int s, int x0, int y0, int H, int W,
   return ply >= 0 && ply < TH && plx >= 0 && plx < TW && py >= 0 && py < H && px >= 0 && px < W;
 }
 
-template <int TW, int TH, int NC, int NT, int NG>
+// Tile configuration: TW x TH output tile, NC filters per LDS chunk, NT threads, adjoint
+// register blocks of BR x BC outputs per thread (NT / ((TH/BR) (TW/BC)) filter groups).
+//
+// LDS layout: u6 holds u+ on the tile + 6 halo.  Each z plane holds z_j = theta_j rho'(y_j) on
+// the tile + 3 halo (R3), surrounded by a zero frame (3 rows above/below, 4 columns left and
+// 4 right), so that the extended samples of the SYMMETRIC fold read 7x7 windows without
+// bounds checks; samples off the image are zero.
+template <int TW, int TH, int NC, int NT, int BR, int BC>
 __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
   constexpr int W6 = TW + 4 * R, H6 = TH + 4 * R;
   constexpr int W3 = TW + 2 * R, H3 = TH + 2 * R;
   constexpr int PLANE3 = H3 * W3;
-  constexpr int GT = NT / NG;              // threads per adjoint group
-  constexpr int FPG = NC / NG;             // filters per group per chunk
-  constexpr int STRIPS = GT / TW;          // strips per column
-  constexpr int STRIP = TH / STRIPS;       // rows per thread
-  constexpr int NS = 6 * TW + 6 * TH + 36; // fold slots
-  constexpr int SLOTS_PT = (NS + NT - 1) / NT;
-  static_assert(GT % TW == 0 && TH % STRIPS == 0 && NC % NG == 0 && GT % 64 == 0, "bad tiling");
-  static_assert(NG * TH * TW + NS <= NC * PLANE3, "epilogue does not fit in the z buffer");
+  constexpr int ZR = R, ZC = R + 1;               // zero frame: rows above, columns left
+  constexpr int W3P = W3 + ZC + R + 1, H3P = H3 + 2 * ZR;  // W3P even for float2 reads
+  constexpr int PLANEP = H3P * W3P;
+  constexpr int PPT = (PLANE3 + NT - 1) / NT;     // forward positions per thread
+  constexpr int GT = (TH / BR) * (TW / BC);       // threads per adjoint group
+  constexpr int NG = NT / GT;                     // filter groups
+  constexpr int FPG = NC / NG;                    // filters per group per chunk
+  constexpr int WR = BR + KS - 1, WC = BC + KS - 1;
+  constexpr int NS = 6 * TW + 6 * TH + 36;        // fold slots
+  constexpr int SLOTS_PT = (NS + GT - 1) / GT;    // compacted fold slots per thread (per group)
+  static_assert(NT % GT == 0 && NC % NG == 0 && GT % 64 == 0 && TH % BR == 0 && TW % BC == 0, "bad tiling");
+  static_assert(BC % 2 == 0 && W3P % 2 == 0 && PLANEP % 2 == 0 && ZC % 2 == 0, "adjoint reads float2 pairs");
+  static_assert(NC % 8 == 0, "forward passes take 8 filters");
+  static_assert(NG * (TH * TW + NS) <= NC * PLANEP, "epilogue does not fit in the z buffer");
+  static_assert(NS <= 2 * NT, "fold slot scan covers at most two slots per thread");
 
   __shared__ float u6[H6 * W6];
-  __shared__ float z3[NC * PLANE3];
+  __shared__ __attribute__((aligned(16))) float zp[NC * PLANEP];
   __shared__ double red[(NT / 64) * 5];
+  __shared__ int act_off[NS];    // compacted fold slots: z-plane offset of the 7x7 window
+  __shared__ short act_slot[NS]; //                       and the slot id
+  __shared__ int wave_cnt[NT / 64];
+  // taps of the current chunk, read by broadcast LDS loads so that the FMAs take them from VGPRs
+  // (a VALU FMA with an SGPR operand issues at half rate on gfx950)
+  constexpr int KAP = 52;                                   // padded adjoint tap stride (16 B rows)
+  __shared__ __attribute__((aligned(16))) float kf_s[KK * NC];   // [t][j]
+  __shared__ __attribute__((aligned(16))) float ka_s[NC * KAP];  // [j][t]
 
   const int tid = threadIdx.x;
   const Problem pb = a.pb;
@@ -147,6 +169,7 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
 
   const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
   const int x0 = tx * TW, y0 = ty * TH;
+  const bool fold = bc == SYMMETRIC && (y0 < R || y0 + TH > H - R || x0 < R || x0 + TW > W - R);
 
   double accF = 0.0, accG = 0.0, accS1 = 0.0, accS2 = 0.0, accM = 0.0;
 
@@ -182,109 +205,181 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
     }
     u6[idx] = uval;
   }
-  __syncthreads();
 
-  // ---- adjoint mapping
+  // ---- fold tiles: zero the z planes (frame stays zero) and compact the non-empty fold slots
+  int n_act = 0;
+  if (fold) {
+    float4* z4 = reinterpret_cast<float4*>(zp);
+    for (int i = tid; i < NC * PLANEP / 4; i += NT) z4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool act[2];
+    int off[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int s = tid + h * NT, ply, plx, qy, qx;
+      act[h] = s < NS && slot_target<TW, TH>(s, x0, y0, H, W, ply, plx, qy, qx);
+      // window top-left (tile coords qy - y0, qx - x0) in z-plane coordinates
+      off[h] = act[h] ? (qy - y0 + ZR) * W3P + (qx - x0 + ZC) : 0;
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+    int base = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      unsigned long long m = __ballot(act[h]);
+      if (lane == 0) wave_cnt[wave] = __popcll(m);
+      __syncthreads();
+      int before = 0, total = 0;
+      for (int w = 0; w < NT / 64; ++w) {
+        int cw = wave_cnt[w];
+        before += w < wave ? cw : 0;
+        total += cw;
+      }
+      int pos = base + before + __popcll(m & ((1ull << lane) - 1ull));
+      if (act[h]) {
+        act_off[pos] = off[h];
+        act_slot[pos] = (short)(tid + h * NT);
+      }
+      base += total;
+      __syncthreads();
+    }
+    n_act = base;
+  }
+
+  // forward positions of this thread (fixed across chunks)
+  int fbase[PPT];      // u6 offset of the window's top-left sample, or -1 when the slot is empty
+  int zofs[PPT];       // z-plane offset of the position
+  bool flive[PPT], fown[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    int idx = tid + k * NT;
+    int r = idx / W3, c = idx - r * W3;
+    int gy = y0 - R + r, gx = x0 - R + c;
+    bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+    fbase[k] = idx < PLANE3 ? r * W6 + c : -1;
+    zofs[k] = (r + ZR) * W3P + c + ZC;
+    flive[k] = idx < PLANE3 && (inimg || bc == PERIODIC);
+    fown[k] = idx < PLANE3 && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
+  }
+
+  // adjoint mapping: group grp takes FPG filters of each chunk; thread owns a BR x BC block
   const int grp = __builtin_amdgcn_readfirstlane(tid / GT);  // wave-uniform (GT % 64 == 0)
   const int lt = tid - grp * GT;
-  const int col = lt % TW;
-  const int row0 = (lt / TW) * STRIP;
-  float acc[STRIP];
+  const int col0 = (lt % (TW / BC)) * BC;
+  const int row0 = (lt / (TW / BC)) * BR;
+  float acc[BR][BC];
 #pragma unroll
-  for (int k = 0; k < STRIP; ++k) acc[k] = 0.0f;
-
-  const bool fold = bc == SYMMETRIC && (y0 < R || y0 + TH > H - R || x0 < R || x0 + TW > W - R);
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) acc[i][j] = 0.0f;
   float sacc[SLOTS_PT];
 #pragma unroll
   for (int k = 0; k < SLOTS_PT; ++k) sacc[k] = 0.0f;
 
+  __syncthreads();
+
   const int nf = pb.nf;
   for (int c0 = 0; c0 < nf; c0 += NC) {
     const int ncur = min(NC, nf - c0);
-    // ---- stage 2: forward bank + rho, rho' on tile + 3 halo -> z3
-    for (int idx = tid; idx < PLANE3; idx += NT) {
-      int r = idx / W3, c = idx - r * W3;
-      int gy = y0 - R + r, gx = x0 - R + c;
-      bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-      if (!inimg && bc != PERIODIC) {
+    for (int t = tid; t < KK * NC; t += NT) kf_s[t] = a.kf[(size_t)c0 * KK + t];
+    for (int t = tid; t < NC * KAP; t += NT) {
+      const int j = t / KAP, tt = t - j * KAP;
+      ka_s[t] = tt < KK ? a.ka[(size_t)(c0 + j) * KK + tt] : 0.0f;
+    }
+    __syncthreads();
+    // ---- stage 2: forward bank on tile + 3 halo; one row of taps of 8 filters (in SGPRs) per pass
+    float y[PPT][NC];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) z3[j * PLANE3 + idx] = 0.0f;
-        continue;
-      }
-      float y[NC];
+    for (int k = 0; k < PPT; ++k)
 #pragma unroll
-      for (int j = 0; j < NC; ++j) y[j] = 0.0f;
-      cfloat* kb = as_const(a.kf) + (size_t)c0 * KK;   // chunk c0 / NC, [t][j]
-      // one filter row at a time keeps 7 x NC taps in SGPRs
+      for (int j = 0; j < NC; ++j) y[k][j] = 0.0f;
+    constexpr int NH = NC / 8;
 #pragma unroll 1
-      for (int ta = 0; ta < KS; ++ta) {
-        float wrow[KS];
+    for (int ta = 0; ta < KS; ++ta) {
 #pragma unroll
-        for (int tb = 0; tb < KS; ++tb) wrow[tb] = u6[(r + ta) * W6 + c + tb];
-        cfloat* kr = kb + ta * KS * NC;
+      for (int h = 0; h < NH; ++h) {
+        float kr[KS * 8];
 #pragma unroll
-        for (int tb = 0; tb < KS; ++tb)
+        for (int tb = 0; tb < KS; ++tb) {
+          const float4* src = reinterpret_cast<const float4*>(kf_s + (ta * KS + tb) * NC + h * 8);
+          float4 p0 = src[0], p1 = src[1];
+          kr[tb * 8 + 0] = p0.x; kr[tb * 8 + 1] = p0.y; kr[tb * 8 + 2] = p0.z; kr[tb * 8 + 3] = p0.w;
+          kr[tb * 8 + 4] = p1.x; kr[tb * 8 + 5] = p1.y; kr[tb * 8 + 6] = p1.z; kr[tb * 8 + 7] = p1.w;
+        }
 #pragma unroll
-          for (int j = 0; j < NC; ++j) y[j] = fmaf(kr[tb * NC + j], wrow[tb], y[j]);
+        for (int k = 0; k < PPT; ++k) {
+          if (fbase[k] < 0) continue;
+          float wrow[KS];
+#pragma unroll
+          for (int tb = 0; tb < KS; ++tb) wrow[tb] = u6[fbase[k] + ta * W6 + tb];
+#pragma unroll
+          for (int tb = 0; tb < KS; ++tb)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) y[k][h * 8 + j] = fmaf(kr[tb * 8 + j], wrow[tb], y[k][h * 8 + j]);
+        }
       }
-      const bool own = inimg && r >= R && r < R + TH && c >= R && c < R + TW;
+    }
+    // rho' into the z planes (zero off the image unless periodic), theta * rho summed over the tile
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (fbase[k] < 0) continue;
       float e = 0.0f;
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
-        float th = j < ncur ? as_const(a.theta)[c0 + j] : 0.0f;
-        float den = fmaf(y[j], y[j], 1.0f);
-        z3[j * PLANE3 + idx] = th * 2.0f * y[j] * fast_rcp(den);
+        float th = j < ncur ? a.theta[c0 + j] : 0.0f;
+        float den = fmaf(y[k][j], y[k][j], 1.0f);
+        float z = th * 2.0f * y[k][j] * fast_rcp(den);
+        zp[j * PLANEP + zofs[k]] = flive[k] ? z : 0.0f;
         e = fmaf(th, fast_log(den), e);
       }
-      if (own) accF += (double)e;
+      if (fown[k]) accF += (double)e;
     }
     __syncthreads();
 
-    // ---- stage 3: adjoint bank on the tile (strips of STRIP rows), group grp takes FPG filters
+    // ---- stage 3: adjoint bank.  Per filter of the group: the BR x BC block of this thread from a
+    // (BR+6) x (BC+6) window in registers, then the fold slots assigned to this thread (7x7 windows
+    // around extended samples; the taps are the same 49 scalars).
 #pragma unroll 1
     for (int jj = 0; jj < FPG; ++jj) {
       const int j = grp * FPG + jj;
       if (j >= ncur) break;
-      cfloat* kj = as_const(a.ka) + (size_t)(c0 + j) * KK;
-      const float* zb = z3 + j * PLANE3;
+      float kt[KAP];
 #pragma unroll
-      for (int tb = 0; tb < KS; ++tb) {
-        float colv[STRIP + KS - 1];
+      for (int t = 0; t < KAP; t += 4) {
+        float4 q4 = *reinterpret_cast<const float4*>(ka_s + j * KAP + t);
+        kt[t] = q4.x; kt[t + 1] = q4.y; kt[t + 2] = q4.z; kt[t + 3] = q4.w;
+      }
+      const float* zplane = zp + j * PLANEP;
+      const float* zb = zplane + (row0 + ZR) * W3P + col0 + ZC;
+      // stream the (BR+6) x (BC+6) window one row at a time; row q feeds output rows q - ta
 #pragma unroll
-        for (int q = 0; q < STRIP + KS - 1; ++q) colv[q] = zb[(row0 + q) * W3 + col + tb];
+      for (int q = 0; q < WR; ++q) {
+        float wrow[WC];
+#pragma unroll
+        for (int s = 0; s < WC; s += 2) {
+          float2 v2 = *reinterpret_cast<const float2*>(zb + q * W3P + s);
+          wrow[s] = v2.x;
+          wrow[s + 1] = v2.y;
+        }
 #pragma unroll
         for (int ta = 0; ta < KS; ++ta) {
-          const float kv = kj[ta * KS + tb];
+          const int i = q - ta;
+          if (i < 0 || i >= BR) continue;
 #pragma unroll
-          for (int k = 0; k < STRIP; ++k) acc[k] = fmaf(kv, colv[k + ta], acc[k]);
+          for (int tb = 0; tb < KS; ++tb)
+#pragma unroll
+            for (int jx = 0; jx < BC; ++jx) acc[i][jx] = fmaf(kt[ta * KS + tb], wrow[jx + tb], acc[i][jx]);
         }
       }
-    }
-    // mirror terms of the SYMMETRIC map: v(q) = sum_j sum_ab k_j[a][b] z_j(q + (a-3, b-3)), z = 0 off the image
-    if (fold) {
+      if (fold) {
 #pragma unroll
-      for (int k = 0; k < SLOTS_PT; ++k) {
-        int s = tid + k * NT;
-        int ply, plx, qy, qx;
-        if (s < NS && slot_target<TW, TH>(s, x0, y0, H, W, ply, plx, qy, qx)) {
+        for (int k = 0; k < SLOTS_PT; ++k) {
+          const int m = lt + k * GT;
+          if (m >= n_act) break;
+          const float* zw = zplane + act_off[m];
           float v = 0.0f;
-          for (int j = 0; j < ncur; ++j) {
-            cfloat* kj = as_const(a.ka) + (size_t)(c0 + j) * KK;
-            const float* zb = z3 + j * PLANE3;
-            for (int ta = 0; ta < KS; ++ta) {
-              int zy = qy - R + ta;
-              if ((unsigned)zy >= (unsigned)H) continue;
-              int r3 = zy - (y0 - R);
-              if ((unsigned)r3 >= (unsigned)H3) continue;
-              for (int tb = 0; tb < KS; ++tb) {
-                int zx = qx - R + tb;
-                if ((unsigned)zx >= (unsigned)W) continue;
-                int c3 = zx - (x0 - R);
-                if ((unsigned)c3 >= (unsigned)W3) continue;
-                v = fmaf(kj[ta * KS + tb], zb[r3 * W3 + c3], v);
-              }
-            }
-          }
+#pragma unroll
+          for (int ta = 0; ta < KS; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < KS; ++tb) v = fmaf(kt[ta * KS + tb], zw[ta * W3P + tb], v);
           sacc[k] += v;
         }
       }
@@ -293,15 +388,19 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
   }
 
   // ---- epilogue: combine groups and fold slots in a fixed order, chain rule, store
-  float* gsum = z3;                       // [NG][TH][TW]
-  float* slots = z3 + NG * TH * TW;       // [NS]
+  float* gsum = zp;                       // [NG][TH][TW]
+  float* slots = zp + NG * TH * TW;       // [NG][NS]
 #pragma unroll
-  for (int k = 0; k < STRIP; ++k) gsum[grp * TH * TW + (row0 + k) * TW + col] = acc[k];
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int jx = 0; jx < BC; ++jx) gsum[grp * TH * TW + (row0 + i) * TW + col0 + jx] = acc[i][jx];
   if (fold) {
+    for (int i = tid; i < NG * NS; i += NT) slots[i] = 0.0f;
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < SLOTS_PT; ++k) {
-      int s = tid + k * NT;
-      if (s < NS) slots[s] = sacc[k];
+      const int m = lt + k * GT;
+      if (m < n_act) slots[grp * NS + act_slot[m]] = sacc[k];
     }
   }
   __syncthreads();
@@ -313,15 +412,19 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
 #pragma unroll
     for (int q = 0; q < NG; ++q) g += gsum[q * TH * TW + idx];
     if (fold) {
-      if (py < R) g += slots[py * TW + jx];
-      if (py >= H - R) g += slots[3 * TW + (H - 1 - py) * TW + jx];
-      if (px < R) g += slots[6 * TW + px * TH + i];
-      if (px >= W - R) g += slots[6 * TW + 3 * TH + (W - 1 - px) * TH + i];
       const int cb = 6 * TW + 6 * TH;
-      if (py < R && px < R) g += slots[cb + 0 * 9 + py * 3 + px];
-      if (py < R && px >= W - R) g += slots[cb + 1 * 9 + py * 3 + (W - 1 - px)];
-      if (py >= H - R && px < R) g += slots[cb + 2 * 9 + (H - 1 - py) * 3 + px];
-      if (py >= H - R && px >= W - R) g += slots[cb + 3 * 9 + (H - 1 - py) * 3 + (W - 1 - px)];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const float* sl = slots + q * NS;
+        if (py < R) g += sl[py * TW + jx];
+        if (py >= H - R) g += sl[3 * TW + (H - 1 - py) * TW + jx];
+        if (px < R) g += sl[6 * TW + px * TH + i];
+        if (px >= W - R) g += sl[6 * TW + 3 * TH + (W - 1 - px) * TH + i];
+        if (py < R && px < R) g += sl[cb + 0 * 9 + py * 3 + px];
+        if (py < R && px >= W - R) g += sl[cb + 1 * 9 + py * 3 + (W - 1 - px)];
+        if (py >= H - R && px < R) g += sl[cb + 2 * 9 + (H - 1 - py) * 3 + px];
+        if (py >= H - R && px >= W - R) g += sl[cb + 3 * 9 + (H - 1 - py) * 3 + (W - 1 - px)];
+      }
     }
     if (logm) g *= u6[(i + 2 * R) * W6 + jx + 2 * R];
     go[(size_t)py * W + px] = g;
