@@ -43,6 +43,7 @@ struct Problem {
   int nf;
   int model, bc, step_mode;
   int max_backtracks, newton_iters;
+  int engine;  // forward-bank engine of the fused kernel
   float lam1, lam2, beta;
   double beta_d, eta_up, eta_down, alpha_fixed;
 };

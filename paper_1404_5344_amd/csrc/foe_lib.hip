@@ -103,7 +103,10 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
 }
 
 void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
-  fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC><<<s->nblocks, V_NT, 0, stream>>>(a);
+  if (s->pb.engine == FWD_MFMA_F32)
+    fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_F32><<<s->nblocks, V_NT, 0, stream>>>(a);
+  else
+    fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU><<<s->nblocks, V_NT, 0, stream>>>(a);
 }
 
 void launch_decide(foe_solver* s, int mode, hipStream_t stream) {
@@ -125,7 +128,7 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   if (p->model < 0 || p->model > 2) return fail(FOE_EINVAL, "bad model");
   if (p->boundary < 0 || p->boundary > 2) return fail(FOE_EINVAL, "bad boundary");
   if (p->precision != FOE_PREC_FP32) return fail(FOE_EINVAL, "precision not supported by this engine");
-  if (p->engine != FOE_ENGINE_AUTO && p->engine != FOE_ENGINE_VALU) return fail(FOE_EINVAL, "engine not available");
+  if (p->engine < FOE_ENGINE_AUTO || p->engine > FOE_ENGINE_MFMA) return fail(FOE_EINVAL, "bad engine");
   if (p->step_mode != FOE_STEP_BACKTRACK && p->step_mode != FOE_STEP_FIXED) return fail(FOE_EINVAL, "bad step_mode");
   if (p->looks < 1) return fail(FOE_EINVAL, "looks must be >= 1");
   if (p->max_iters < 0) return fail(FOE_EINVAL, "max_iters must be >= 0");
@@ -168,6 +171,7 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   pb->eta_up = p->eta_up;
   pb->eta_down = p->eta_down;
   pb->alpha_fixed = p->alpha_fixed;
+  pb->engine = p->engine == FOE_ENGINE_VALU ? FWD_VALU : FWD_MFMA_F32;
   return FOE_OK;
 }
 

@@ -19,6 +19,8 @@
 namespace foe {
 
 enum FusedMode { MODE_TRIAL = 0, MODE_EVAL = 1 };
+enum ForwardEngine { FWD_VALU = 0, FWD_MFMA_F32 = 1 };
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct FusedArgs {
   Problem pb;
@@ -108,7 +110,7 @@ __device__ __forceinline__ bool slot_target(int s, int x0, int y0, int H, int W,
 // the tile + 3 halo (R3), surrounded by a zero frame (3 rows above/below, 4 columns left and
 // 4 right), so that the extended samples of the SYMMETRIC fold read 7x7 windows without
 // bounds checks; samples off the image are zero.
-template <int TW, int TH, int NC, int NT, int BR, int BC>
+template <int TW, int TH, int NC, int NT, int BR, int BC, int FWD>
 __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
   constexpr int W6 = TW + 4 * R, H6 = TH + 4 * R;
   constexpr int W3 = TW + 2 * R, H3 = TH + 2 * R;
@@ -128,6 +130,8 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
   static_assert(NC % 8 == 0, "forward passes take 8 filters");
   static_assert(NG * (TH * TW + NS) <= NC * PLANEP, "epilogue does not fit in the z buffer");
   static_assert(NS <= 2 * NT, "fold slot scan covers at most two slots per thread");
+  static_assert(FWD == FWD_VALU || NC == 16, "the MFMA forward takes one 16-filter block per chunk");
+  constexpr int NGROUP = (PLANE3 + 15) / 16;      // MFMA forward: groups of 16 consecutive positions
 
   __shared__ float u6[H6 * W6];
   __shared__ __attribute__((aligned(16))) float zp[NC * PLANEP];
@@ -285,52 +289,98 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
       ka_s[t] = tt < KK ? a.ka[(size_t)(c0 + j) * KK + tt] : 0.0f;
     }
     __syncthreads();
-    // ---- stage 2: forward bank on tile + 3 halo; one row of taps of 8 filters (in SGPRs) per pass
-    float y[PPT][NC];
+    if constexpr (FWD == FWD_MFMA_F32) {
+      // ---- stage 2 (matrix cores): per group of 16 consecutive R3 positions,
+      // Y^T[16 filters x 16 positions] = Kflip^T[16 x 52 taps] . X[52 taps x 16 positions] with
+      // v_mfma_f32_16x16x4f32 (taps 49..51 carry zero weight).  Lane (m = lane % 16, k = lane / 16)
+      // holds the A value Kflip[filter m][tap 4s + k] and the B value u6 at tap 4s + k of position m;
+      // the result lands as y for position m, filters 4k .. 4k + 3.
+      const int lane = tid & 63, wave = tid >> 6, lm = lane & 15, lk = lane >> 4;
+      float a_reg[13];
+      int toff[13];
 #pragma unroll
-    for (int k = 0; k < PPT; ++k)
+      for (int s = 0; s < 13; ++s) {
+        const int t = 4 * s + lk;
+        a_reg[s] = t < KK ? kf_s[t * NC + lm] : 0.0f;
+        toff[s] = t < KK ? (t / KS) * W6 + (t % KS) : 0;
+      }
+      float thv[4];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) y[k][j] = 0.0f;
-    constexpr int NH = NC / 8;
+      for (int j = 0; j < 4; ++j) thv[j] = 4 * lk + j < ncur ? a.theta[c0 + 4 * lk + j] : 0.0f;
 #pragma unroll 1
-    for (int ta = 0; ta < KS; ++ta) {
+      for (int g = wave; g < NGROUP; g += NT / 64) {
+        const int p = g * 16 + lm;
+        const bool inr = p < PLANE3;
+        const int r = inr ? p / W3 : 0, c = inr ? p - (p / W3) * W3 : 0;
+        const int pbase = r * W6 + c;
+        floatx4 acc4 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int h = 0; h < NH; ++h) {
-        float kr[KS * 8];
+        for (int s = 0; s < 13; ++s)
+          acc4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a_reg[s], u6[pbase + toff[s]], acc4, 0, 0, 0);
+        const int gy = y0 - R + r, gx = x0 - R + c;
+        const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+        const bool live = inr && (inimg || bc == PERIODIC);
+        const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
+        const int zo = (r + ZR) * W3P + c + ZC;
+        float e = 0.0f;
 #pragma unroll
-        for (int tb = 0; tb < KS; ++tb) {
-          const float4* src = reinterpret_cast<const float4*>(kf_s + (ta * KS + tb) * NC + h * 8);
-          float4 p0 = src[0], p1 = src[1];
-          kr[tb * 8 + 0] = p0.x; kr[tb * 8 + 1] = p0.y; kr[tb * 8 + 2] = p0.z; kr[tb * 8 + 3] = p0.w;
-          kr[tb * 8 + 4] = p1.x; kr[tb * 8 + 5] = p1.y; kr[tb * 8 + 6] = p1.z; kr[tb * 8 + 7] = p1.w;
+        for (int j = 0; j < 4; ++j) {
+          const float yv = acc4[j];
+          const float den = fmaf(yv, yv, 1.0f);
+          const float z = thv[j] * 2.0f * yv * fast_rcp(den);
+          if (inr) zp[(4 * lk + j) * PLANEP + zo] = live ? z : 0.0f;
+          e = fmaf(thv[j], fast_log(den), e);
         }
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          if (fbase[k] < 0) continue;
-          float wrow[KS];
-#pragma unroll
-          for (int tb = 0; tb < KS; ++tb) wrow[tb] = u6[fbase[k] + ta * W6 + tb];
-#pragma unroll
-          for (int tb = 0; tb < KS; ++tb)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) y[k][h * 8 + j] = fmaf(kr[tb * 8 + j], wrow[tb], y[k][h * 8 + j]);
+        if (own) accF += (double)e;
+      }
+    } else {
+      // ---- stage 2: forward bank on tile + 3 halo; one row of taps of 8 filters (in SGPRs) per pass
+      float y[PPT][NC];
+  #pragma unroll
+      for (int k = 0; k < PPT; ++k)
+  #pragma unroll
+        for (int j = 0; j < NC; ++j) y[k][j] = 0.0f;
+      constexpr int NH = NC / 8;
+  #pragma unroll 1
+      for (int ta = 0; ta < KS; ++ta) {
+  #pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          float kr[KS * 8];
+  #pragma unroll
+          for (int tb = 0; tb < KS; ++tb) {
+            const float4* src = reinterpret_cast<const float4*>(kf_s + (ta * KS + tb) * NC + h * 8);
+            float4 p0 = src[0], p1 = src[1];
+            kr[tb * 8 + 0] = p0.x; kr[tb * 8 + 1] = p0.y; kr[tb * 8 + 2] = p0.z; kr[tb * 8 + 3] = p0.w;
+            kr[tb * 8 + 4] = p1.x; kr[tb * 8 + 5] = p1.y; kr[tb * 8 + 6] = p1.z; kr[tb * 8 + 7] = p1.w;
+          }
+  #pragma unroll
+          for (int k = 0; k < PPT; ++k) {
+            if (fbase[k] < 0) continue;
+            float wrow[KS];
+  #pragma unroll
+            for (int tb = 0; tb < KS; ++tb) wrow[tb] = u6[fbase[k] + ta * W6 + tb];
+  #pragma unroll
+            for (int tb = 0; tb < KS; ++tb)
+  #pragma unroll
+              for (int j = 0; j < 8; ++j) y[k][h * 8 + j] = fmaf(kr[tb * 8 + j], wrow[tb], y[k][h * 8 + j]);
+          }
         }
       }
-    }
-    // rho' into the z planes (zero off the image unless periodic), theta * rho summed over the tile
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      if (fbase[k] < 0) continue;
-      float e = 0.0f;
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        float th = j < ncur ? a.theta[c0 + j] : 0.0f;
-        float den = fmaf(y[k][j], y[k][j], 1.0f);
-        float z = th * 2.0f * y[k][j] * fast_rcp(den);
-        zp[j * PLANEP + zofs[k]] = flive[k] ? z : 0.0f;
-        e = fmaf(th, fast_log(den), e);
+      // rho' into the z planes (zero off the image unless periodic), theta * rho summed over the tile
+  #pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        if (fbase[k] < 0) continue;
+        float e = 0.0f;
+  #pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          float th = j < ncur ? a.theta[c0 + j] : 0.0f;
+          float den = fmaf(y[k][j], y[k][j], 1.0f);
+          float z = th * 2.0f * y[k][j] * fast_rcp(den);
+          zp[j * PLANEP + zofs[k]] = flive[k] ? z : 0.0f;
+          e = fmaf(th, fast_log(den), e);
+        }
+        if (fown[k]) accF += (double)e;
       }
-      if (fown[k]) accF += (double)e;
     }
     __syncthreads();
 

@@ -27,17 +27,21 @@ def _gpu(t, dev):
     return torch.from_numpy(np.ascontiguousarray(t, dtype=np.float32)).to(dev)
 
 
+ENGINES = [1, 2]   # FOE_ENGINE_VALU, FOE_ENGINE_MFMA (forward bank on matrix cores)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("shape", SIZES)
-def test_gradient_and_energy(model, bc, shape):
+def test_gradient_and_energy(model, bc, shape, engine):
     torch, dev = torch_dev()
     H, W = shape
     clean, f = speckled(H, W, seed=H * 1000 + W)
     bank, theta = bank_and_theta("random" if (H + W + bc) % 2 else "dct", seed=H + W)
     x = state_for(model, f)
     l1, l2 = LAMS[model]
-    s = make_solver(H, W, bank, theta, model=model, boundary=bc, lambda1=l1, lambda2=l2)
+    s = make_solver(H, W, bank, theta, model=model, boundary=bc, lambda1=l1, lambda2=l2, engine=engine)
     g = s.eval_gradient(_gpu(x, dev)).cpu().numpy()
     g_ora = oracle.grad_F(x, bank, theta, model, bc)
     assert rel_inf(g, g_ora) <= 1e-4, (model, bc, shape, rel_inf(g, g_ora))
@@ -70,9 +74,10 @@ def test_prox(model):
     s.close()
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("bc", BCS)
-def test_step_teacher_forced(model, bc):
+def test_step_teacher_forced(model, bc, engine):
     torch, dev = torch_dev()
     H, W = 70, 45
     clean, f = speckled(H, W, looks=4, seed=11)
@@ -85,7 +90,7 @@ def test_step_teacher_forced(model, bc):
     x = res.x.astype(np.float32)
     xp = res.x_prev.astype(np.float32)
     L = float(res.L)
-    s = make_solver(H, W, bank, theta, model=model, boundary=bc, lambda1=l1, lambda2=l2)
+    s = make_solver(H, W, bank, theta, model=model, boundary=bc, lambda1=l1, lambda2=l2, engine=engine)
     xn, info = s.step(_gpu(f, dev), _gpu(x, dev), _gpu(xp, dev), L)
     xn = xn.cpu().numpy()
     xn_ora, info_ora = oracle.step(po, f, bank, theta, x, xp, L)
@@ -106,14 +111,16 @@ def test_step_teacher_forced(model, bc):
     s.close()
 
 
-def test_random_filters_and_fewer_filters():
-    """Nothing may rely on the DCT bank: random non-separable filters, 13 filters (ragged chunk)."""
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("nf", [13, 48, 64])
+def test_random_filters_and_filter_counts(nf, engine):
+    """Nothing may rely on the DCT bank: random non-separable filters; 13 filters (ragged chunk), 64 (maximum)."""
     torch, dev = torch_dev()
     H, W = 45, 77
     clean, f = speckled(H, W, seed=3)
-    bank, theta = bank_and_theta("random", nf=13, seed=7)
+    bank, theta = bank_and_theta("random", nf=nf, seed=7)
     x = state_for(oracle.COMBINED, f)
-    s = make_solver(H, W, bank, theta)
+    s = make_solver(H, W, bank, theta, engine=engine)
     g = s.eval_gradient(_gpu(x, dev)).cpu().numpy()
     assert rel_inf(g, oracle.grad_F(x, bank, theta)) <= 1e-4
     s.close()
