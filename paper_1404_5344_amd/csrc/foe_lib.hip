@@ -103,7 +103,9 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
 }
 
 void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
-  if (s->pb.engine == FWD_MFMA_F32)
+  if (s->pb.engine == FWD_MFMA_BF16)
+    fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16><<<s->nblocks, V_NT, 0, stream>>>(a);
+  else if (s->pb.engine == FWD_MFMA_F32)
     fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_F32><<<s->nblocks, V_NT, 0, stream>>>(a);
   else
     fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU><<<s->nblocks, V_NT, 0, stream>>>(a);
@@ -127,7 +129,9 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   if (p->ksize != FOE_KSIZE) return fail(FOE_EINVAL, "ksize must be 7");
   if (p->model < 0 || p->model > 2) return fail(FOE_EINVAL, "bad model");
   if (p->boundary < 0 || p->boundary > 2) return fail(FOE_EINVAL, "bad boundary");
-  if (p->precision != FOE_PREC_FP32) return fail(FOE_EINVAL, "precision not supported by this engine");
+  if (p->precision != FOE_PREC_FP32 && p->precision != FOE_PREC_BF16) return fail(FOE_EINVAL, "bad precision");
+  if (p->precision == FOE_PREC_BF16 && p->engine == FOE_ENGINE_VALU)
+    return fail(FOE_EINVAL, "BF16 precision runs on the MFMA engine");
   if (p->engine < FOE_ENGINE_AUTO || p->engine > FOE_ENGINE_MFMA) return fail(FOE_EINVAL, "bad engine");
   if (p->step_mode != FOE_STEP_BACKTRACK && p->step_mode != FOE_STEP_FIXED) return fail(FOE_EINVAL, "bad step_mode");
   if (p->looks < 1) return fail(FOE_EINVAL, "looks must be >= 1");
@@ -171,7 +175,8 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   pb->eta_up = p->eta_up;
   pb->eta_down = p->eta_down;
   pb->alpha_fixed = p->alpha_fixed;
-  pb->engine = p->engine == FOE_ENGINE_VALU ? FWD_VALU : FWD_MFMA_F32;
+  pb->engine = p->precision == FOE_PREC_BF16 ? FWD_MFMA_BF16
+               : (p->engine == FOE_ENGINE_VALU ? FWD_VALU : FWD_MFMA_F32);
   return FOE_OK;
 }
 

@@ -19,8 +19,9 @@
 namespace foe {
 
 enum FusedMode { MODE_TRIAL = 0, MODE_EVAL = 1 };
-enum ForwardEngine { FWD_VALU = 0, FWD_MFMA_F32 = 1 };
+enum ForwardEngine { FWD_VALU = 0, FWD_MFMA_F32 = 1, FWD_MFMA_BF16 = 2 };
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct FusedArgs {
   Problem pb;
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
   static_assert(NC % 8 == 0, "forward passes take 8 filters");
   static_assert(NG * (TH * TW + NS) <= NC * PLANEP, "epilogue does not fit in the z buffer");
   static_assert(NS <= 2 * NT, "fold slot scan covers at most two slots per thread");
-  static_assert(FWD == FWD_VALU || NC == 16, "the MFMA forward takes one 16-filter block per chunk");
+  static_assert(FWD == FWD_VALU || NC == 16, "the MFMA forwards take one 16-filter block per chunk");
   constexpr int NGROUP = (PLANE3 + 15) / 16;      // MFMA forward: groups of 16 consecutive positions
 
   __shared__ float u6[H6 * W6];
@@ -289,7 +290,76 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
       ka_s[t] = tt < KK ? a.ka[(size_t)(c0 + j) * KK + tt] : 0.0f;
     }
     __syncthreads();
-    if constexpr (FWD == FWD_MFMA_F32) {
+    if constexpr (FWD == FWD_MFMA_BF16) {
+      // ---- stage 2 (matrix cores, BF16 operands, FP32 accumulation): v_mfma_f32_16x16x32_bf16 with
+      // lane (m = lane % 16, k = lane / 16) holding taps 32s + 8k .. 32s + 8k + 7 of filter m (A) and the
+      // same taps of position m (B).  The B values are differences u(p + t) - u(p) to the position's own
+      // sample, so that BF16 rounding acts on local contrast and not on the 8-bit intensity level
+      // (zero-sum filters applied to flat regions would otherwise drown in rounding noise); the exact
+      // FP32 term u(p) * sum_t k[t] is added back after the product.  Each operand is split into a BF16
+      // head and a BF16 tail (x = hi + lo), and three products hi*hi + hi*lo + lo*hi are accumulated,
+      // which keeps the energies of the line search at close to FP32 accuracy.
+      const int lane = tid & 63, wave = tid >> 6, lm = lane & 15, lk = lane >> 4;
+      bf16x8 a16[2], a16lo[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int t = 32 * s + 8 * lk + i;
+          const float kv = t < KK ? kf_s[t * NC + lm] : 0.0f;
+          a16[s][i] = (__bf16)kv;
+          a16lo[s][i] = (__bf16)(kv - (float)a16[s][i]);
+        }
+      float thv[4], ksum[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int fj = 4 * lk + j;
+        thv[j] = fj < ncur ? a.theta[c0 + fj] : 0.0f;
+        float sum = 0.0f;
+        for (int t = 0; t < KK; ++t) sum += kf_s[t * NC + fj];
+        ksum[j] = sum;
+      }
+#pragma unroll 1
+      for (int g = wave; g < NGROUP; g += NT / 64) {
+        const int p = g * 16 + lm;
+        const bool inr = p < PLANE3;
+        const int r = inr ? p / W3 : 0, c = inr ? p - (p / W3) * W3 : 0;
+        const int pbase = r * W6 + c;
+        const float uc = u6[pbase + R * W6 + R];
+        floatx4 acc4 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          bf16x8 b16, b16lo;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int t = 32 * s + 8 * lk + i;
+            const int toff = t < KK ? (t / KS) * W6 + (t % KS) : 0;
+            const float d = u6[pbase + toff] - uc;
+            b16[i] = (__bf16)d;
+            b16lo[i] = (__bf16)(d - (float)b16[i]);
+          }
+          acc4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a16lo[s], b16, acc4, 0, 0, 0);
+          acc4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a16[s], b16lo, acc4, 0, 0, 0);
+          acc4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a16[s], b16, acc4, 0, 0, 0);
+        }
+        const int gy = y0 - R + r, gx = x0 - R + c;
+        const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+        const bool live = inr && (inimg || bc == PERIODIC);
+        const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
+        const int zo = (r + ZR) * W3P + c + ZC;
+        // the position's u(p) is the same for the 4 filters of this lane; fetch it per lane
+        float e = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float yv = fmaf(uc, ksum[j], acc4[j]);
+          const float den = fmaf(yv, yv, 1.0f);
+          const float z = thv[j] * 2.0f * yv * fast_rcp(den);
+          if (inr) zp[(4 * lk + j) * PLANEP + zo] = live ? z : 0.0f;
+          e = fmaf(thv[j], fast_log(den), e);
+        }
+        if (own) accF += (double)e;
+      }
+    } else if constexpr (FWD == FWD_MFMA_F32) {
       // ---- stage 2 (matrix cores): per group of 16 consecutive R3 positions,
       // Y^T[16 filters x 16 positions] = Kflip^T[16 x 52 taps] . X[52 taps x 16 positions] with
       // v_mfma_f32_16x16x4f32 (taps 49..51 carry zero weight).  Lane (m = lane % 16, k = lane / 16)
