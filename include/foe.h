@@ -130,6 +130,35 @@ foe_status foe_solve(foe_solver* s, const float* d_f, const float* d_init, float
 foe_status foe_solve_from(foe_solver* s, const float* d_f, float* d_x_cur, float* d_x_prev, double* L_inout,
                           int32_t iters, foe_summary* sum_host, double* stats_host);
 
+/* ---- Batches of images of uneven sizes (one fused launch over the tiles of all images per
+ * trial, one decide block per image; per-image lambda, step size, Lipschitz estimate and
+ * energies live on the device; every iteration round is replayed from HIP graphs).
+ * shared: the parameters common to all images (height/width/looks/lambda fields ignored);
+ * heights, widths, looks: [n]; lambda1, lambda2: [n] or NULL (=> the paper's values per looks).
+ * Images are passed as packed planes: image i occupies floats [off_i, off_i + H_i W_i) with
+ * off_0 = 0, off_{i+1} = off_i + H_i W_i (foe_batch_layout returns the n + 1 offsets).  The
+ * handle is a foe_solver; foe_destroy releases it; foe_solve_from / foe_eval_energy accept
+ * batch handles with per-image arrays (L_inout[n], F[n], G[n]). */
+foe_status foe_batch_create(const foe_params* shared, int32_t n, const int32_t* heights, const int32_t* widths,
+                            const double* lambda1, const double* lambda2, const int32_t* looks,
+                            const float* filters_host, const float* weights_host, void* hip_stream,
+                            foe_solver** out);
+foe_status foe_batch_layout(foe_solver* s, int32_t* n_images, int64_t* offsets_host /* [n+1], nullable */);
+/* Solve every image of the batch (max_iters iterations each).  d_init nullable (packed u^0).
+ * sums_host: [n] summaries (nullable); stats_host: [n][max_iters][8] (nullable).
+ * Returns the first failing image's status; the other images are still solved. */
+foe_status foe_batch_solve(foe_solver* s, const float* d_f, const float* d_init, float* d_u_out,
+                           foe_summary* sums_host, double* stats_host);
+
+/* ---- Tile-shape autotuner.  Times `reps` fused trial launches of each tile configuration
+ * (32x32, 32x16 output tiles) on the solver's images with input d_f (packed), keeps the
+ * fastest, and records it in the file named by the environment variable FOE_TUNE_CACHE
+ * (when set; keyed by engine, boundary, filter count and the sorted image sizes) so later
+ * solvers with the same key skip the timing.  *chosen receives the configuration index.
+ * Results do not depend on the configuration beyond floating-point summation order. */
+foe_status foe_autotune(foe_solver* s, const float* d_f, int32_t reps, int32_t* chosen);
+foe_status foe_set_tile_config(foe_solver* s, int32_t cfg);
+
 /* Probes running the same kernels as the solve path. */
 /* d_grad = grad F(d_x). */
 foe_status foe_eval_gradient(foe_solver* s, const float* d_x, float* d_grad);

@@ -51,6 +51,10 @@ _DP = ctypes.POINTER(ctypes.c_double)
 
 
 def _load():
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).  Loading torch
+    # first makes the library bind to that runtime, so device pointers and streams of torch and
+    # of the library belong to one HIP runtime in the process.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_1404_5344_amd/build.py)")
     L = ctypes.CDLL(LIB_PATH)
@@ -66,13 +70,21 @@ def _load():
     L.foe_step.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _DP]
     L.foe_last_timing.argtypes = [_VP, _DP, ctypes.POINTER(ctypes.c_int32)]
     L.foe_profile_trial.argtypes = [_VP, ctypes.c_int32, _DP]
+    _IP = ctypes.POINTER(ctypes.c_int32)
+    L.foe_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, _IP, _IP, _DP, _DP, _IP, _VP, _VP, _VP,
+                                   ctypes.POINTER(_VP)]
+    L.foe_batch_layout.argtypes = [_VP, _IP, ctypes.POINTER(ctypes.c_int64)]
+    L.foe_batch_solve.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(Summary), _DP]
+    L.foe_autotune.argtypes = [_VP, _VP, ctypes.c_int32, _IP]
+    L.foe_set_tile_config.argtypes = [_VP, ctypes.c_int32]
     L.foe_status_str.argtypes = [ctypes.c_int]
     L.foe_status_str.restype = ctypes.c_char_p
     L.foe_last_error.argtypes = []
     L.foe_last_error.restype = ctypes.c_char_p
     L.foe_abi_version.restype = ctypes.c_int32
     for name in ("foe_create", "foe_destroy", "foe_solve", "foe_solve_from", "foe_eval_gradient", "foe_eval_energy",
-                 "foe_eval_prox", "foe_step", "foe_last_timing", "foe_profile_trial"):
+                 "foe_eval_prox", "foe_step", "foe_last_timing", "foe_profile_trial", "foe_batch_create",
+                 "foe_batch_layout", "foe_batch_solve", "foe_autotune", "foe_set_tile_config"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -228,8 +240,71 @@ class Solver:
         _check(lib.foe_profile_trial(self._h, int(reps), ctypes.byref(ms)))
         return ms.value
 
+    def autotune(self, f, reps: int = 3) -> int:
+        """Pick the fastest tile configuration for this solver's images (see foe_autotune)."""
+        self._sync_in()
+        c = ctypes.c_int32(-1)
+        _check(lib.foe_autotune(self._h, _dev_ptr(f, None, "f"), int(reps), ctypes.byref(c)))
+        return c.value
+
+    def set_tile_config(self, cfg: int):
+        _check(lib.foe_set_tile_config(self._h, int(cfg)))
+
     def last_timing(self):
         ms = ctypes.c_double()
         n = ctypes.c_int32()
         _check(lib.foe_last_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class BatchSolver(Solver):
+    """Many images of uneven sizes solved together; images are packed planes (see foe.h)."""
+
+    def __init__(self, params: Params, sizes, looks, filters, weights, lambda1=None, lambda2=None, stream=None):
+        torch = _torch()
+        self.params = params
+        n = len(sizes)
+        self.sizes = [(int(h), int(w)) for h, w in sizes]
+        k = np.ascontiguousarray(np.asarray(filters, dtype=np.float32).reshape(-1, 7, 7))
+        th = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).reshape(-1))
+        self._k, self._th = k, th
+        Hs = (ctypes.c_int32 * n)(*[h for h, _ in self.sizes])
+        Ws = (ctypes.c_int32 * n)(*[w for _, w in self.sizes])
+        Ls = (ctypes.c_int32 * n)(*[int(x) for x in looks])
+        l1 = (ctypes.c_double * n)(*lambda1) if lambda1 is not None else None
+        l2 = (ctypes.c_double * n)(*lambda2) if lambda2 is not None else None
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _VP()
+        _check(lib.foe_batch_create(ctypes.byref(params), n, Hs, Ws, l1, l2, Ls, k.ctypes.data_as(_VP),
+                                    th.ctypes.data_as(_VP), _VP(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.n_images = n
+        offs = (ctypes.c_int64 * (n + 1))()
+        _check(lib.foe_batch_layout(self._h, None, offs))
+        self.offsets = [int(o) for o in offs]
+        self.shape = (self.offsets[-1],)
+
+    def pack(self, images):
+        torch = _torch()
+        return torch.cat([torch.as_tensor(im, dtype=torch.float32).reshape(-1) for im in images]).contiguous()
+
+    def unpack(self, packed):
+        return [packed[self.offsets[i]:self.offsets[i + 1]].reshape(self.sizes[i]) for i in range(self.n_images)]
+
+    def solve(self, f_packed, init=None, out=None, allow_failure=False):
+        torch = _torch()
+        self._sync_in()
+        if out is None:
+            out = torch.empty_like(f_packed)
+        n = self.n_images
+        sums = (Summary * n)()
+        rows = max(self.params.max_iters, 1)
+        stats = np.zeros((n, rows, STATS_COLS))
+        st = lib.foe_batch_solve(self._h, _dev_ptr(f_packed, self.shape, "f"),
+                                 _dev_ptr(init, self.shape, "init") if init is not None else None,
+                                 _dev_ptr(out, self.shape, "out"), sums, stats.ctypes.data_as(_DP))
+        _check(st, (OK, ELINESEARCH, ENONFINITE) if allow_failure else (OK,))
+        summaries = [sums[i].as_dict() for i in range(n)]
+        return out, summaries, [stats[i, :summaries[i]["iters_done"]].copy() for i in range(n)], st

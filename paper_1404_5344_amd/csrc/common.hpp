@@ -37,14 +37,28 @@ struct DevState {
   int pad_;
 };
 
-// Solver-wide constants of one image.
+// One image of a (possibly single-image) batch: packed-plane offset, size, data-term weights and
+// its range in the tile list.
+struct ImageDesc {
+  long long off;
+  int H, W;
+  float lam1, lam2;
+  int tile0, ntiles;
+};
+
+// One output tile of the flattened tile list over all images.
+struct TileDesc {
+  int image, x0, y0, pad;
+};
+
+// Solver-wide constants (shared by every image of a batch).
 struct Problem {
   int H, W;
   int nf;
   int model, bc, step_mode;
   int max_backtracks, newton_iters;
   int engine;  // forward-bank engine of the fused kernel
-  float lam1, lam2, beta;
+  float beta;
   double beta_d, eta_up, eta_down, alpha_fixed;
 };
 

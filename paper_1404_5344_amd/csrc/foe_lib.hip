@@ -1,17 +1,24 @@
 // Host runtime and C ABI of the FoE + iPiano library (declared in include/foe.h).
 //
-// A solver owns, per image: the x ring (x^n, x^{n-1}, candidate), the gradient ring
-// (grad F(x^n), candidate grad F(x+)), a copy of f, per-block partial sums, the device
-// iPiano state and the stats ring.  The iteration loop is a sequence of "slots", each one
-// fused trial launch followed by one single-block decide launch; the decision lives on the
-// device, so the host only synchronises between rounds of slots (one round when no trial
-// is rejected).  Rounds are replayed from pre-instantiated HIP graphs of 16 and 1 slots.
+// A solver owns one image or a batch of images of uneven sizes, stored as packed planes
+// (the images concatenated in index order).  Per solver: the x ring (x^n, x^{n-1},
+// candidate), the gradient ring (grad F(x^n), candidate grad F(x+)), a copy of f, the
+// flattened list of output tiles over all images, per-tile partial sums, one device iPiano
+// state per image and the stats rings.  The iteration loop is a sequence of "slots": one
+// fused trial launch over every tile of every image, then one decide launch with one block
+// per image.  Decisions live on the device, so the host only synchronises between rounds
+// of slots (one round when no trial is rejected); an image whose iterations are done turns
+// its tiles into no-ops.  Rounds are replayed from pre-instantiated HIP graphs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -38,8 +45,13 @@ foe_status fail(foe_status st, const std::string& msg) {
       return fail(FOE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));                 \
   } while (0)
 
-// Default tile configuration of the VALU engine.
-constexpr int V_TW = 32, V_TH = 32, V_NC = 16, V_NT = 512, V_BR = 4, V_BC = 2;
+// Tile configurations of the fused kernel (chosen per solver, by the autotuner if asked).
+constexpr int V_NC = 16, V_NT = 512, V_BR = 4, V_BC = 2;
+struct TileCfg {
+  int tw, th;
+};
+constexpr TileCfg TILE_CFGS[2] = {{32, 32}, {32, 16}};
+constexpr int N_TILE_CFGS = 2;
 constexpr int GRAPH_BIG = 16;
 
 // The paper's lambda1, lambda2 for L = 1, 3, 8 looks (Sec. III-B); other L are interpolated
@@ -63,19 +75,27 @@ struct foe_solver {
   Problem pb{};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
-  size_t n = 0;
+  int n_img = 0;
+  size_t n = 0;  // total pixels
+  std::vector<ImageDesc> images;
+  std::vector<TileDesc> tiles;
+  int tile_cfg = 0;
+  int nblocks = 0;
+  ImageDesc* d_images = nullptr;
+  TileDesc* d_tiles = nullptr;
   float* xr[3] = {nullptr, nullptr, nullptr};
   float* gr[2] = {nullptr, nullptr};
   float* fbuf = nullptr;
-  float* scratch = nullptr;  // probe workspace (one plane)
+  float* scratch = nullptr;  // probe workspace (one packed plane)
   float* kf = nullptr;
   float* ka = nullptr;
   float* theta = nullptr;
   double* partials = nullptr;
-  double* stats = nullptr;
-  DevState* st = nullptr;
-  DevState* st_host = nullptr;  // pinned mirror
-  int tiles_x = 0, tiles_y = 0, nblocks = 0;
+  int max_tiles = 0;
+  double* stats = nullptr;  // [n_img][max_iters][8]
+  int stats_rows = 1;
+  DevState* st = nullptr;       // [n_img]
+  DevState* st_host = nullptr;  // pinned mirror [n_img]
   hipGraphExec_t graph_big = nullptr, graph_one = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
@@ -84,9 +104,31 @@ struct foe_solver {
 
 namespace {
 
+void build_tiles(foe_solver* s, int cfg) {
+  const TileCfg tc = TILE_CFGS[cfg];
+  s->tiles.clear();
+  for (int i = 0; i < s->n_img; ++i) {
+    ImageDesc& im = s->images[i];
+    im.tile0 = (int)s->tiles.size();
+    for (int y = 0; y < im.H; y += tc.th)
+      for (int x = 0; x < im.W; x += tc.tw) s->tiles.push_back(TileDesc{i, x, y, 0});
+    im.ntiles = (int)s->tiles.size() - im.tile0;
+  }
+  s->tile_cfg = cfg;
+  s->nblocks = (int)s->tiles.size();
+}
+
+foe_status upload_tiles(foe_solver* s) {
+  HIP_OR(hipMemcpy(s->d_images, s->images.data(), sizeof(ImageDesc) * s->n_img, hipMemcpyHostToDevice));
+  HIP_OR(hipMemcpy(s->d_tiles, s->tiles.data(), sizeof(TileDesc) * s->nblocks, hipMemcpyHostToDevice));
+  return FOE_OK;
+}
+
 FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in, float* g_out) {
   FusedArgs a;
   a.pb = s->pb;
+  a.tiles = s->d_tiles;
+  a.images = s->d_images;
   a.f = f;
   a.xr0 = s->xr[0]; a.xr1 = s->xr[1]; a.xr2 = s->xr[2];
   a.gr0 = s->gr[0]; a.gr1 = s->gr[1];
@@ -97,22 +139,36 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
   a.kf = s->kf;
   a.ka = s->ka;
   a.theta = s->theta;
-  a.tiles_x = s->tiles_x;
   a.mode = mode;
   return a;
 }
 
-void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
+template <int TW, int TH>
+void launch_cfg(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
   if (s->pb.engine == FWD_MFMA_BF16)
-    fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16><<<s->nblocks, V_NT, 0, stream>>>(a);
+    fused_valu_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16><<<s->nblocks, V_NT, 0, stream>>>(a);
   else if (s->pb.engine == FWD_MFMA_F32)
-    fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_F32><<<s->nblocks, V_NT, 0, stream>>>(a);
+    fused_valu_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_F32><<<s->nblocks, V_NT, 0, stream>>>(a);
   else
-    fused_valu_kernel<V_TW, V_TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU><<<s->nblocks, V_NT, 0, stream>>>(a);
+    fused_valu_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU><<<s->nblocks, V_NT, 0, stream>>>(a);
+}
+
+void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
+  if (s->tile_cfg == 1)
+    launch_cfg<32, 16>(s, a, stream);
+  else
+    launch_cfg<32, 32>(s, a, stream);
 }
 
 void launch_decide(foe_solver* s, int mode, hipStream_t stream) {
-  decide_kernel<<<1, 256, 0, stream>>>(s->st, s->partials, s->nblocks, s->pb, s->stats, mode);
+  decide_kernel<<<s->n_img, 256, 0, stream>>>(s->st, s->partials, s->d_images, s->pb, s->stats, s->stats_rows, mode);
+}
+
+dim3 grid_img(const foe_solver* s) {
+  size_t mx = 0;
+  for (const ImageDesc& im : s->images) mx = std::max(mx, (size_t)im.H * im.W);
+  size_t b = (mx + 255) / 256;
+  return dim3((unsigned)std::min<size_t>(std::max<size_t>(b, 1), 1024), (unsigned)s->n_img, 1);
 }
 
 int grid_1d(size_t n) {
@@ -120,21 +176,19 @@ int grid_1d(size_t n) {
   return (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
 }
 
+// Validates the parameters shared by every image and fills the shared Problem.
 foe_status validate(const foe_params* p, const float* filters, const float* weights, Problem* pb) {
   if (!p) return fail(FOE_EINVAL, "params is NULL");
   if (!filters || !weights) return fail(FOE_EINVAL, "filters/weights is NULL");
-  if (p->height < 4 || p->width < 4) return fail(FOE_EINVAL, "height and width must be >= 4");
-  if ((int64_t)p->height * p->width > ((int64_t)1 << 31)) return fail(FOE_EINVAL, "image too large");
   if (p->num_filters < 1 || p->num_filters > FOE_MAX_FILTERS) return fail(FOE_EINVAL, "num_filters out of range");
   if (p->ksize != FOE_KSIZE) return fail(FOE_EINVAL, "ksize must be 7");
   if (p->model < 0 || p->model > 2) return fail(FOE_EINVAL, "bad model");
   if (p->boundary < 0 || p->boundary > 2) return fail(FOE_EINVAL, "bad boundary");
   if (p->precision != FOE_PREC_FP32 && p->precision != FOE_PREC_BF16) return fail(FOE_EINVAL, "bad precision");
+  if (p->engine < FOE_ENGINE_AUTO || p->engine > FOE_ENGINE_MFMA) return fail(FOE_EINVAL, "bad engine");
   if (p->precision == FOE_PREC_BF16 && p->engine == FOE_ENGINE_VALU)
     return fail(FOE_EINVAL, "BF16 precision runs on the MFMA engine");
-  if (p->engine < FOE_ENGINE_AUTO || p->engine > FOE_ENGINE_MFMA) return fail(FOE_EINVAL, "bad engine");
   if (p->step_mode != FOE_STEP_BACKTRACK && p->step_mode != FOE_STEP_FIXED) return fail(FOE_EINVAL, "bad step_mode");
-  if (p->looks < 1) return fail(FOE_EINVAL, "looks must be >= 1");
   if (p->max_iters < 0) return fail(FOE_EINVAL, "max_iters must be >= 0");
   if (p->max_backtracks < 0) return fail(FOE_EINVAL, "max_backtracks must be >= 0");
   if (p->newton_iters < 1 || p->newton_iters > 100) return fail(FOE_EINVAL, "newton_iters must be in [1, 100]");
@@ -145,31 +199,16 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
     if (!(std::isfinite(p->eta_up) && p->eta_up > 1.0)) return fail(FOE_EINVAL, "eta_up must be > 1");
     if (!(p->eta_down > 0.0 && p->eta_down <= 1.0)) return fail(FOE_EINVAL, "eta_down must be in (0, 1]");
   }
-  double l1 = p->lambda1, l2 = p->lambda2;
-  if (p->model == FOE_MODEL_IDIV) {
-    if (!(std::isfinite(l1) && l1 >= 0.0)) return fail(FOE_EINVAL, "IDIV needs lambda1 >= 0");
-  } else {
-    double d1, d2;
-    paper_lambdas(p->looks, &d1, &d2);
-    if (l1 < 0.0) l1 = d1;
-    if (l2 < 0.0) l2 = d2;
-    if (!std::isfinite(l1) || !std::isfinite(l2)) return fail(FOE_EINVAL, "lambda must be finite");
-  }
-  if (p->model == FOE_MODEL_LOG) l2 = 0.0;
   for (int i = 0; i < p->num_filters * FOE_KSIZE * FOE_KSIZE; ++i)
     if (!std::isfinite(filters[i])) return fail(FOE_EINVAL, "non-finite filter tap");
   for (int i = 0; i < p->num_filters; ++i)
     if (!(std::isfinite(weights[i]) && weights[i] >= 0.0f)) return fail(FOE_EINVAL, "weights must be finite, >= 0");
-  pb->H = p->height;
-  pb->W = p->width;
   pb->nf = p->num_filters;
   pb->model = p->model;
   pb->bc = p->boundary;
   pb->step_mode = p->step_mode;
   pb->max_backtracks = p->max_backtracks;
   pb->newton_iters = p->newton_iters;
-  pb->lam1 = (float)l1;
-  pb->lam2 = (float)l2;
   pb->beta = (float)p->beta;
   pb->beta_d = p->beta;
   pb->eta_up = p->eta_up;
@@ -180,25 +219,47 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   return FOE_OK;
 }
 
+// Per-image size and data-term weights (lambda < 0 => the paper's value for `looks`).
+foe_status image_desc(const foe_params* p, int H, int W, double l1, double l2, int looks, ImageDesc* im) {
+  if (H < 4 || W < 4) return fail(FOE_EINVAL, "height and width must be >= 4");
+  if ((int64_t)H * W > ((int64_t)1 << 31)) return fail(FOE_EINVAL, "image too large");
+  if (looks < 1) return fail(FOE_EINVAL, "looks must be >= 1");
+  if (p->model == FOE_MODEL_IDIV) {
+    if (!(std::isfinite(l1) && l1 >= 0.0)) return fail(FOE_EINVAL, "IDIV needs lambda1 >= 0");
+  } else {
+    double d1, d2;
+    paper_lambdas(looks, &d1, &d2);
+    if (l1 < 0.0) l1 = d1;
+    if (l2 < 0.0) l2 = d2;
+    if (!std::isfinite(l1) || !std::isfinite(l2)) return fail(FOE_EINVAL, "lambda must be finite");
+  }
+  if (p->model != FOE_MODEL_COMBINED) l2 = 0.0;
+  im->H = H;
+  im->W = W;
+  im->lam1 = (float)l1;
+  im->lam2 = (float)l2;
+  return FOE_OK;
+}
+
 void destroy_all(foe_solver* s) {
   if (!s) return;
   if (s->graph_big) (void)hipGraphExecDestroy(s->graph_big);
   if (s->graph_one) (void)hipGraphExecDestroy(s->graph_one);
   for (float* p : s->xr) if (p) (void)hipFree(p);
   for (float* p : s->gr) if (p) (void)hipFree(p);
-  if (s->fbuf) (void)hipFree(s->fbuf);
-  if (s->scratch) (void)hipFree(s->scratch);
-  if (s->kf) (void)hipFree(s->kf);
-  if (s->ka) (void)hipFree(s->ka);
-  if (s->theta) (void)hipFree(s->theta);
-  if (s->partials) (void)hipFree(s->partials);
-  if (s->stats) (void)hipFree(s->stats);
-  if (s->st) (void)hipFree(s->st);
+  void* bufs[] = {s->fbuf, s->scratch, s->kf, s->ka, s->theta, s->partials, s->stats, s->st, s->d_images, s->d_tiles};
+  for (void* b : bufs) if (b) (void)hipFree(b);
   if (s->st_host) (void)hipHostFree(s->st_host);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
+}
+
+void drop_graphs(foe_solver* s) {
+  if (s->graph_big) (void)hipGraphExecDestroy(s->graph_big);
+  if (s->graph_one) (void)hipGraphExecDestroy(s->graph_one);
+  s->graph_big = s->graph_one = nullptr;
 }
 
 foe_status build_graph(foe_solver* s, int slots, hipGraphExec_t* out) {
@@ -216,50 +277,81 @@ foe_status build_graph(foe_solver* s, int slots, hipGraphExec_t* out) {
   return FOE_OK;
 }
 
-// Host-side initial device state for a launch sequence of `iters` iterations from ring slots 0/1.
-void reset_state(foe_solver* s, double L_in, int iters) {
-  DevState& h = *s->st_host;
-  std::memset(&h, 0, sizeof(DevState));
-  h.icur = 0; h.iprev = 1; h.icand = 2;
-  h.gcur = 0; h.gcand = 1;
-  h.target = iters;
-  if (s->pb.step_mode == FIXED) {
-    h.L = L_in;
-    h.alpha = s->pb.alpha_fixed;
-  } else {
-    h.L = s->pb.eta_down * L_in;
-    h.alpha = 1.9 * (1.0 - s->pb.beta_d) / h.L;
+// Host-side initial device state of every image for a launch sequence of `iters` iterations
+// from ring slots 0 (x^n) and 1 (x^{n-1}).
+void reset_states(foe_solver* s, const double* L_in, int iters) {
+  for (int i = 0; i < s->n_img; ++i) {
+    DevState& h = s->st_host[i];
+    std::memset(&h, 0, sizeof(DevState));
+    h.icur = 0; h.iprev = 1; h.icand = 2;
+    h.gcur = 0; h.gcand = 1;
+    h.target = iters;
+    if (s->pb.step_mode == FIXED) {
+      h.L = L_in[i];
+      h.alpha = s->pb.alpha_fixed;
+    } else {
+      h.L = s->pb.eta_down * L_in[i];
+      h.alpha = 1.9 * (1.0 - s->pb.beta_d) / h.L;
+    }
+    h.L_acc = L_in[i];
   }
-  h.L_acc = L_in;
 }
 
-// Runs the iteration loop from ring slots 0 (x^n) and 1 (x^{n-1}); fbuf holds f.
-foe_status run_loop(foe_solver* s, double L_in, int iters, foe_summary* sum, double* stats_host) {
-  reset_state(s, L_in, iters);
-  HIP_OR(hipMemcpyAsync(s->st, s->st_host, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
+foe_status push_states(foe_solver* s) {
+  HIP_OR(hipMemcpyAsync(s->st, s->st_host, sizeof(DevState) * s->n_img, hipMemcpyHostToDevice, s->stream));
+  return FOE_OK;
+}
+
+foe_status pull_states(foe_solver* s) {
+  HIP_OR(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState) * s->n_img, hipMemcpyDeviceToHost, s->stream));
+  HIP_OR(hipStreamSynchronize(s->stream));
+  return FOE_OK;
+}
+
+foe_status status_of(int st) {
+  switch (st) {
+    case ST_OK: return FOE_OK;
+    case ST_ELINESEARCH: return fail(FOE_ELINESEARCH, "backtracking exceeded max_backtracks");
+    case ST_ENONFINITE: return fail(FOE_ENONFINITE, "non-finite energy or reduction");
+    case ST_EINPUT: return fail(FOE_EINPUT, "f or the initial image has a non-finite or non-positive pixel");
+    default: return fail(FOE_EDEVICE, "unknown device status");
+  }
+}
+
+// Runs the iteration loop of every image from ring slots 0 / 1; fbuf holds f.  Summaries and
+// stats are per image.  Returns the first image's failure status, if any.
+foe_status run_loop(foe_solver* s, const double* L_in, int iters, foe_summary* sums, double* stats_host) {
+  reset_states(s, L_in, iters);
+  foe_status e = push_states(s);
+  if (e != FOE_OK) return e;
   // F, G and grad F at x^0
   launch_fused(s, fused_args(s, MODE_EVAL, s->fbuf, s->xr[0], s->gr[0]), s->stream);
   launch_decide(s, DECIDE_INIT, s->stream);
   HIP_OR(hipGetLastError());
   if (!s->graph_big) {
-    foe_status e = build_graph(s, GRAPH_BIG, &s->graph_big);
+    e = build_graph(s, GRAPH_BIG, &s->graph_big);
     if (e != FOE_OK) return e;
     e = build_graph(s, 1, &s->graph_one);
     if (e != FOE_OK) return e;
   }
   HIP_OR(hipEventRecord(s->ev0, s->stream));
-  int remaining = iters;
+  e = pull_states(s);
+  if (e != FOE_OK) return e;
+  std::vector<double> G0(s->n_img);
+  for (int i = 0; i < s->n_img; ++i) G0[i] = s->st_host[i].sums[1];
   int launches = 0;
-  HIP_OR(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
-  HIP_OR(hipStreamSynchronize(s->stream));
-  double G0 = s->st_host->sums[1];
-  while (remaining > 0 && !s->st_host->done) {
+  for (;;) {
+    int remaining = 0;
+    for (int i = 0; i < s->n_img; ++i) {
+      const DevState& h = s->st_host[i];
+      if (!h.done) remaining = std::max(remaining, h.target - h.iter);
+    }
+    if (remaining <= 0) break;
     for (int k = 0; k < remaining / GRAPH_BIG; ++k) HIP_OR(hipGraphLaunch(s->graph_big, s->stream));
     for (int k = 0; k < remaining % GRAPH_BIG; ++k) HIP_OR(hipGraphLaunch(s->graph_one, s->stream));
     launches += remaining;
-    HIP_OR(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
-    HIP_OR(hipStreamSynchronize(s->stream));
-    remaining = s->st_host->target - s->st_host->iter;
+    e = pull_states(s);
+    if (e != FOE_OK) return e;
   }
   HIP_OR(hipEventRecord(s->ev1, s->stream));
   HIP_OR(hipEventSynchronize(s->ev1));
@@ -267,32 +359,141 @@ foe_status run_loop(foe_solver* s, double L_in, int iters, foe_summary* sum, dou
   HIP_OR(hipEventElapsedTime(&ms, s->ev0, s->ev1));
   s->last_ms = ms;
   s->last_launches = launches;
-  const DevState& h = *s->st_host;
-  if (stats_host && h.iter > 0)
-    HIP_OR(hipMemcpy(stats_host, s->stats, sizeof(double) * STAT_COLS * h.iter, hipMemcpyDeviceToHost));
-  if (sum) {
-    sum->iters_done = h.iter;
-    sum->total_trials = h.total_trials;
-    sum->F = h.Fcur;
-    if (h.iter > 0) {
-      double row[STAT_COLS];
-      HIP_OR(hipMemcpy(row, s->stats + (size_t)(h.iter - 1) * STAT_COLS, sizeof(row), hipMemcpyDeviceToHost));
-      sum->G = row[1];
-      sum->alpha = row[3];
-    } else {
-      sum->G = G0;
-      sum->alpha = h.alpha;
+  std::vector<double> rows;
+  if (stats_host || sums) {
+    rows.resize((size_t)s->n_img * s->stats_rows * STAT_COLS);
+    HIP_OR(hipMemcpy(rows.data(), s->stats, sizeof(double) * rows.size(), hipMemcpyDeviceToHost));
+  }
+  foe_status first = FOE_OK;
+  for (int i = 0; i < s->n_img; ++i) {
+    const DevState& h = s->st_host[i];
+    const double* ri = rows.empty() ? nullptr : rows.data() + (size_t)i * s->stats_rows * STAT_COLS;
+    if (stats_host && h.iter > 0)
+      std::memcpy(stats_host + (size_t)i * s->stats_rows * STAT_COLS, ri, sizeof(double) * STAT_COLS * h.iter);
+    if (sums) {
+      foe_summary& sm = sums[i];
+      sm.iters_done = h.iter;
+      sm.total_trials = h.total_trials;
+      sm.F = h.Fcur;
+      sm.G = h.iter > 0 ? ri[(size_t)(h.iter - 1) * STAT_COLS + 1] : G0[i];
+      sm.alpha = h.iter > 0 ? ri[(size_t)(h.iter - 1) * STAT_COLS + 3] : h.alpha;
+      sm.H = sm.F + sm.G;
+      sm.L = h.L_acc;
     }
-    sum->H = sum->F + sum->G;
-    sum->L = h.L_acc;
+    if (h.status != ST_OK && first == FOE_OK) first = status_of(h.status);
   }
-  switch (h.status) {
-    case ST_OK: return FOE_OK;
-    case ST_ELINESEARCH: return fail(FOE_ELINESEARCH, "backtracking exceeded max_backtracks");
-    case ST_ENONFINITE: return fail(FOE_ENONFINITE, "non-finite energy or reduction");
-    case ST_EINPUT: return fail(FOE_EINPUT, "f or the initial image has a non-finite or non-positive pixel");
-    default: return fail(FOE_EDEVICE, "unknown device status");
+  return first;
+}
+
+foe_status create_common(const foe_params* p, int n_img, const int32_t* H, const int32_t* W, const double* l1,
+                         const double* l2, const int32_t* looks, const float* filters_host,
+                         const float* weights_host, void* hip_stream, foe_solver** out) {
+  if (!out) return fail(FOE_EINVAL, "out is NULL");
+  if (n_img < 1) return fail(FOE_EINVAL, "need at least one image");
+  Problem pb;
+  foe_status v = validate(p, filters_host, weights_host, &pb);
+  if (v != FOE_OK) return v;
+  std::vector<ImageDesc> images(n_img);
+  long long off = 0;
+  for (int i = 0; i < n_img; ++i) {
+    v = image_desc(p, H[i], W[i], l1[i], l2[i], looks[i], &images[i]);
+    if (v != FOE_OK) return v;
+    images[i].off = off;
+    off += (long long)H[i] * W[i];
   }
+  foe_solver* s = new (std::nothrow) foe_solver();
+  if (!s) return fail(FOE_ENOMEM, "host allocation failed");
+  s->p = *p;
+  s->pb = pb;
+  s->stream = (hipStream_t)hip_stream;
+  s->n_img = n_img;
+  s->n = (size_t)off;
+  s->images = images;
+  // the tile list of the configuration with the most tiles bounds the partials buffer
+  for (int c = 0; c < N_TILE_CFGS; ++c) {
+    build_tiles(s, c);
+    s->max_tiles = std::max(s->max_tiles, s->nblocks);
+  }
+  build_tiles(s, 0);
+  s->stats_rows = p->max_iters > 0 ? p->max_iters : 1;
+  const size_t plane = sizeof(float) * s->n;
+  std::string alloc_err;
+  auto alloc = [&](void** ptr, size_t bytes) -> bool {
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) alloc_err = std::to_string(bytes) + " bytes: " + hipGetErrorString(e);
+    return e == hipSuccess;
+  };
+  bool ok = true;
+  for (auto& x : s->xr) ok = ok && alloc((void**)&x, plane);
+  for (auto& g : s->gr) ok = ok && alloc((void**)&g, plane);
+  ok = ok && alloc((void**)&s->fbuf, plane) && alloc((void**)&s->scratch, plane);
+  ok = ok && alloc((void**)&s->kf, sizeof(float) * MAX_NF * KK) && alloc((void**)&s->ka, sizeof(float) * MAX_NF * KK);
+  ok = ok && alloc((void**)&s->theta, sizeof(float) * MAX_NF);
+  ok = ok && alloc((void**)&s->partials, sizeof(double) * PART_COLS * (size_t)s->max_tiles);
+  ok = ok && alloc((void**)&s->stats, sizeof(double) * STAT_COLS * (size_t)s->stats_rows * n_img);
+  ok = ok && alloc((void**)&s->st, sizeof(DevState) * n_img);
+  ok = ok && alloc((void**)&s->d_images, sizeof(ImageDesc) * n_img);
+  ok = ok && alloc((void**)&s->d_tiles, sizeof(TileDesc) * (size_t)s->max_tiles);
+  ok = ok && hipHostMalloc((void**)&s->st_host, sizeof(DevState) * n_img, hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    destroy_all(s);
+    return fail(FOE_ENOMEM, "device allocation failed (" + alloc_err + ")");
+  }
+  std::vector<float> kf(MAX_NF * KK, 0.0f), ka(MAX_NF * KK, 0.0f), th(MAX_NF, 0.0f);
+  for (int i = 0; i < p->num_filters; ++i) {
+    th[i] = weights_host[i];
+    for (int a = 0; a < KS; ++a)
+      for (int b = 0; b < KS; ++b) {
+        float k = filters_host[(size_t)i * KK + a * KS + b];
+        ka[i * KK + a * KS + b] = k;
+        const int c = i / V_NC, j = i % V_NC, t = (KS - 1 - a) * KS + (KS - 1 - b);
+        kf[((size_t)c * KK + t) * V_NC + j] = k;
+      }
+  }
+  hipError_t e = hipMemcpy(s->kf, kf.data(), sizeof(float) * kf.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->ka, ka.data(), sizeof(float) * ka.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->theta, th.data(), sizeof(float) * th.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreate(&s->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&s->ev1);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    destroy_all(s);
+    return fail(FOE_EDEVICE, std::string("foe_create: ") + hipGetErrorString(e));
+  }
+  v = upload_tiles(s);
+  if (v != FOE_OK) {
+    destroy_all(s);
+    return v;
+  }
+  *out = s;
+  return FOE_OK;
+}
+
+foe_status init_from_f(foe_solver* s, const float* d_f, const float* d_u0, bool* bad) {
+  HIP_OR(hipMemcpyAsync(s->fbuf, d_f, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
+  std::vector<double> L(s->n_img, s->p.L0);
+  reset_states(s, L.data(), s->p.max_iters);  // ring slot 0 = x^0 even if the input is rejected
+  foe_status e = push_states(s);
+  if (e != FOE_OK) return e;
+  init_state_kernel<<<grid_img(s), 256, 0, s->stream>>>(s->fbuf, d_u0, s->xr[0], s->xr[1], s->d_images,
+                                                        s->pb.model, s->st);
+  HIP_OR(hipGetLastError());
+  e = pull_states(s);
+  if (e != FOE_OK) return e;
+  *bad = false;
+  for (int i = 0; i < s->n_img; ++i) *bad = *bad || s->st_host[i].input_bad;
+  return FOE_OK;
+}
+
+// Key of the autotuner cache: engine and the sorted image sizes.
+std::string tune_key(const foe_solver* s) {
+  std::vector<std::pair<int, int>> sz;
+  for (const ImageDesc& im : s->images) sz.push_back({im.H, im.W});
+  std::sort(sz.begin(), sz.end());
+  std::ostringstream o;
+  o << "e" << s->pb.engine << "_bc" << s->pb.bc << "_nf" << s->pb.nf;
+  for (auto& q : sz) o << "_" << q.first << "x" << q.second;
+  return o.str();
 }
 
 }  // namespace
@@ -324,57 +525,34 @@ void foe_default_params(foe_params* p) {
 
 foe_status foe_create(const foe_params* p, const float* filters_host, const float* weights_host, void* hip_stream,
                       foe_solver** out) {
-  if (!out) return fail(FOE_EINVAL, "out is NULL");
-  Problem pb;
-  foe_status v = validate(p, filters_host, weights_host, &pb);
-  if (v != FOE_OK) return v;
-  foe_solver* s = new (std::nothrow) foe_solver();
-  if (!s) return fail(FOE_ENOMEM, "host allocation failed");
-  s->p = *p;
-  s->pb = pb;
-  s->stream = (hipStream_t)hip_stream;
-  s->n = (size_t)p->height * p->width;
-  s->tiles_x = (p->width + V_TW - 1) / V_TW;
-  s->tiles_y = (p->height + V_TH - 1) / V_TH;
-  s->nblocks = s->tiles_x * s->tiles_y;
-  const size_t plane = sizeof(float) * s->n;
-  auto alloc = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, bytes) == hipSuccess; };
-  bool ok = true;
-  for (auto& x : s->xr) ok = ok && alloc((void**)&x, plane);
-  for (auto& g : s->gr) ok = ok && alloc((void**)&g, plane);
-  ok = ok && alloc((void**)&s->fbuf, plane) && alloc((void**)&s->scratch, plane);
-  ok = ok && alloc((void**)&s->kf, sizeof(float) * MAX_NF * KK) && alloc((void**)&s->ka, sizeof(float) * MAX_NF * KK);
-  ok = ok && alloc((void**)&s->theta, sizeof(float) * MAX_NF);
-  ok = ok && alloc((void**)&s->partials, sizeof(double) * PART_COLS * (size_t)s->nblocks);
-  ok = ok && alloc((void**)&s->stats, sizeof(double) * STAT_COLS * (size_t)(p->max_iters > 0 ? p->max_iters : 1));
-  ok = ok && alloc((void**)&s->st, sizeof(DevState));
-  ok = ok && hipHostMalloc((void**)&s->st_host, sizeof(DevState), hipHostMallocDefault) == hipSuccess;
-  if (!ok) {
-    destroy_all(s);
-    return fail(FOE_ENOMEM, "device allocation failed");
+  if (!p) return fail(FOE_EINVAL, "params is NULL");
+  const int32_t H = p->height, W = p->width, L = p->looks;
+  const double l1 = p->lambda1, l2 = p->lambda2;
+  return create_common(p, 1, &H, &W, &l1, &l2, &L, filters_host, weights_host, hip_stream, out);
+}
+
+foe_status foe_batch_create(const foe_params* shared, int32_t n, const int32_t* heights, const int32_t* widths,
+                            const double* lambda1, const double* lambda2, const int32_t* looks,
+                            const float* filters_host, const float* weights_host, void* hip_stream,
+                            foe_solver** out) {
+  if (!shared || !heights || !widths || !looks) return fail(FOE_EINVAL, "NULL argument");
+  if (n < 1 || n > 65535) return fail(FOE_EINVAL, "batch size must be in [1, 65535]");
+  std::vector<double> l1(n, -1.0), l2(n, -1.0);
+  for (int i = 0; i < n; ++i) {
+    if (lambda1) l1[i] = lambda1[i];
+    if (lambda2) l2[i] = lambda2[i];
   }
-  std::vector<float> kf(MAX_NF * KK, 0.0f), ka(MAX_NF * KK, 0.0f), th(MAX_NF, 0.0f);
-  for (int i = 0; i < p->num_filters; ++i) {
-    th[i] = weights_host[i];
-    for (int a = 0; a < KS; ++a)
-      for (int b = 0; b < KS; ++b) {
-        float k = filters_host[(size_t)i * KK + a * KS + b];
-        ka[i * KK + a * KS + b] = k;
-        const int c = i / V_NC, j = i % V_NC, t = (KS - 1 - a) * KS + (KS - 1 - b);
-        kf[((size_t)c * KK + t) * V_NC + j] = k;
-      }
+  return create_common(shared, n, heights, widths, l1.data(), l2.data(), looks, filters_host, weights_host,
+                       hip_stream, out);
+}
+
+foe_status foe_batch_layout(foe_solver* s, int32_t* n_images, int64_t* offsets_host) {
+  if (!s) return fail(FOE_EINVAL, "solver is NULL");
+  if (n_images) *n_images = s->n_img;
+  if (offsets_host) {
+    for (int i = 0; i < s->n_img; ++i) offsets_host[i] = s->images[i].off;
+    offsets_host[s->n_img] = (int64_t)s->n;
   }
-  hipError_t e = hipMemcpy(s->kf, kf.data(), sizeof(float) * kf.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(s->ka, ka.data(), sizeof(float) * ka.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(s->theta, th.data(), sizeof(float) * th.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipEventCreate(&s->ev0);
-  if (e == hipSuccess) e = hipEventCreate(&s->ev1);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    destroy_all(s);
-    return fail(FOE_EDEVICE, std::string("foe_create: ") + hipGetErrorString(e));
-  }
-  *out = s;
   return FOE_OK;
 }
 
@@ -385,57 +563,62 @@ foe_status foe_destroy(foe_solver* s) {
   return FOE_OK;
 }
 
-foe_status foe_solve(foe_solver* s, const float* d_f, const float* d_init, float* d_u_out, foe_summary* sum_host,
-                     double* stats_host) {
+foe_status foe_batch_solve(foe_solver* s, const float* d_f, const float* d_init, float* d_u_out,
+                           foe_summary* sums_host, double* stats_host) {
   if (!s || !d_f || !d_u_out) return fail(FOE_EINVAL, "NULL argument");
-  HIP_OR(hipMemcpyAsync(s->fbuf, d_f, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
-  reset_state(s, s->p.L0, s->p.max_iters);  // ring slot 0 = x^0 even if the input is rejected
-  HIP_OR(hipMemcpyAsync(s->st, s->st_host, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
-  init_state_kernel<<<grid_1d(s->n), 256, 0, s->stream>>>(s->fbuf, d_init, s->xr[0], s->xr[1], s->n, s->pb.model,
-                                                          s->st);
-  // run_loop resets the state struct; carry the input flag through it
-  HIP_OR(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
-  HIP_OR(hipStreamSynchronize(s->stream));
-  const int bad = s->st_host->input_bad;
-  foe_status st;
+  bool bad = false;
+  foe_status st = init_from_f(s, d_f, d_init, &bad);
+  if (st != FOE_OK) return st;
   if (bad) {
     st = fail(FOE_EINPUT, "f or the initial image has a non-finite or non-positive pixel");
-    if (sum_host) std::memset(sum_host, 0, sizeof(*sum_host));
+    if (sums_host) std::memset(sums_host, 0, sizeof(foe_summary) * s->n_img);
   } else {
-    st = run_loop(s, s->p.L0, s->p.max_iters, sum_host, stats_host);
+    std::vector<double> L(s->n_img, s->p.L0);
+    st = run_loop(s, L.data(), s->p.max_iters, sums_host, stats_host);
   }
-  finalize_kernel<<<grid_1d(s->n), 256, 0, s->stream>>>(s->st, s->xr[0], s->xr[1], s->xr[2], d_u_out, s->n,
-                                                        s->pb.model);
+  finalize_kernel<<<grid_img(s), 256, 0, s->stream>>>(s->st, s->xr[0], s->xr[1], s->xr[2], d_u_out, s->d_images,
+                                                      s->pb.model);
   HIP_OR(hipGetLastError());
   HIP_OR(hipStreamSynchronize(s->stream));
   return st;
+}
+
+foe_status foe_solve(foe_solver* s, const float* d_f, const float* d_init, float* d_u_out, foe_summary* sum_host,
+                     double* stats_host) {
+  if (s && s->n_img != 1) return fail(FOE_EINVAL, "batch solver: use foe_batch_solve");
+  return foe_batch_solve(s, d_f, d_init, d_u_out, sum_host, stats_host);
 }
 
 foe_status foe_solve_from(foe_solver* s, const float* d_f, float* d_x_cur, float* d_x_prev, double* L_inout,
                           int32_t iters, foe_summary* sum_host, double* stats_host) {
   if (!s || !d_f || !d_x_cur || !d_x_prev || !L_inout) return fail(FOE_EINVAL, "NULL argument");
   if (iters < 0 || iters > s->p.max_iters) return fail(FOE_EINVAL, "iters must be in [0, max_iters]");
-  if (!finite_pos(*L_inout)) return fail(FOE_EINVAL, "L must be > 0");
+  for (int i = 0; i < s->n_img; ++i)
+    if (!finite_pos(L_inout[i])) return fail(FOE_EINVAL, "L must be > 0");
   HIP_OR(hipMemcpyAsync(s->fbuf, d_f, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
   HIP_OR(hipMemcpyAsync(s->xr[0], d_x_cur, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
   HIP_OR(hipMemcpyAsync(s->xr[1], d_x_prev, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
-  HIP_OR(hipMemsetAsync(&s->st->input_bad, 0, sizeof(int), s->stream));
-  check_input_kernel<<<grid_1d(s->n), 256, 0, s->stream>>>(s->fbuf, s->n, s->st);
-  HIP_OR(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
-  HIP_OR(hipStreamSynchronize(s->stream));
-  if (s->st_host->input_bad) return fail(FOE_EINPUT, "f has a non-finite or non-positive pixel");
-  foe_status st = run_loop(s, *L_inout, iters, sum_host, stats_host);
-  export_state_kernel<<<grid_1d(s->n), 256, 0, s->stream>>>(s->st, s->xr[0], s->xr[1], s->xr[2], d_x_cur, d_x_prev,
-                                                            s->n);
+  reset_states(s, L_inout, iters);
+  foe_status e = push_states(s);
+  if (e != FOE_OK) return e;
+  check_input_kernel<<<grid_img(s), 256, 0, s->stream>>>(s->fbuf, s->d_images, s->st);
+  HIP_OR(hipGetLastError());
+  e = pull_states(s);
+  if (e != FOE_OK) return e;
+  for (int i = 0; i < s->n_img; ++i)
+    if (s->st_host[i].input_bad) return fail(FOE_EINPUT, "f has a non-finite or non-positive pixel");
+  foe_status st = run_loop(s, L_inout, iters, sum_host, stats_host);
+  export_state_kernel<<<grid_img(s), 256, 0, s->stream>>>(s->st, s->xr[0], s->xr[1], s->xr[2], d_x_cur, d_x_prev,
+                                                          s->d_images);
   HIP_OR(hipGetLastError());
   HIP_OR(hipStreamSynchronize(s->stream));
-  *L_inout = s->st_host->L_acc;
+  for (int i = 0; i < s->n_img; ++i) L_inout[i] = s->st_host[i].L_acc;
   return st;
 }
 
 foe_status foe_eval_gradient(foe_solver* s, const float* d_x, float* d_grad) {
   if (!s || !d_x || !d_grad) return fail(FOE_EINVAL, "NULL argument");
-  // G is not needed; f = x keeps the data-term arithmetic finite
+  // G is not reported; f = x keeps the data-term arithmetic finite
   launch_fused(s, fused_args(s, MODE_EVAL, d_x, d_x, d_grad), s->stream);
   HIP_OR(hipGetLastError());
   HIP_OR(hipStreamSynchronize(s->stream));
@@ -447,17 +630,21 @@ foe_status foe_eval_energy(foe_solver* s, const float* d_x, const float* d_f, do
   launch_fused(s, fused_args(s, MODE_EVAL, d_f, d_x, s->scratch), s->stream);
   launch_decide(s, DECIDE_REPORT, s->stream);
   HIP_OR(hipGetLastError());
-  HIP_OR(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
-  HIP_OR(hipStreamSynchronize(s->stream));
-  if (F) *F = s->st_host->sums[0];
-  if (G) *G = s->st_host->sums[1];
+  foe_status e = pull_states(s);
+  if (e != FOE_OK) return e;
+  for (int i = 0; i < s->n_img; ++i) {
+    if (F) F[i] = s->st_host[i].sums[0];
+    if (G) G[i] = s->st_host[i].sums[1];
+  }
   return FOE_OK;
 }
 
 foe_status foe_eval_prox(foe_solver* s, const float* d_xhat, const float* d_f, double tau, float* d_out) {
   if (!s || !d_xhat || !d_f || !d_out) return fail(FOE_EINVAL, "NULL argument");
+  if (s->n_img != 1) return fail(FOE_EINVAL, "prox probe takes a single-image solver");
   if (!finite_pos(tau)) return fail(FOE_EINVAL, "tau must be > 0");
-  prox_probe_kernel<<<grid_1d(s->n), 256, 0, s->stream>>>(d_xhat, d_f, d_out, s->n, (float)tau, s->pb);
+  prox_probe_kernel<<<grid_1d(s->n), 256, 0, s->stream>>>(d_xhat, d_f, d_out, s->n, (float)tau, s->pb,
+                                                          s->images[0].lam1, s->images[0].lam2);
   HIP_OR(hipGetLastError());
   HIP_OR(hipStreamSynchronize(s->stream));
   return FOE_OK;
@@ -466,24 +653,26 @@ foe_status foe_eval_prox(foe_solver* s, const float* d_xhat, const float* d_f, d
 foe_status foe_step(foe_solver* s, const float* d_f, const float* d_x, const float* d_xprev, double L_forced,
                     float* d_xnext, double* info_host) {
   if (!s || !d_f || !d_x || !d_xprev || !d_xnext) return fail(FOE_EINVAL, "NULL argument");
+  if (s->n_img != 1) return fail(FOE_EINVAL, "step probe takes a single-image solver");
   if (s->pb.step_mode == BACKTRACK && !finite_pos(L_forced)) return fail(FOE_EINVAL, "L_forced must be > 0");
   // ring: slot 0 = x, slot 1 = xprev, slot 2 = output; gradient of x into gr[0]
   HIP_OR(hipMemcpyAsync(s->fbuf, d_f, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
   HIP_OR(hipMemcpyAsync(s->xr[0], d_x, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
   HIP_OR(hipMemcpyAsync(s->xr[1], d_xprev, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
   launch_fused(s, fused_args(s, MODE_EVAL, s->fbuf, s->xr[0], s->gr[0]), s->stream);
-  DevState& h = *s->st_host;
+  DevState& h = s->st_host[0];
   std::memset(&h, 0, sizeof(DevState));
   h.icur = 0; h.iprev = 1; h.icand = 2; h.gcur = 0; h.gcand = 1; h.target = 1;
   h.L = L_forced;
   h.alpha = s->pb.step_mode == FIXED ? s->pb.alpha_fixed : 1.9 * (1.0 - s->pb.beta_d) / L_forced;
-  HIP_OR(hipMemcpyAsync(s->st, s->st_host, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
+  foe_status e = push_states(s);
+  if (e != FOE_OK) return e;
   launch_fused(s, fused_args(s, MODE_TRIAL, s->fbuf, nullptr, nullptr), s->stream);
   launch_decide(s, DECIDE_REPORT, s->stream);
   HIP_OR(hipGetLastError());
   HIP_OR(hipMemcpyAsync(d_xnext, s->xr[2], sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
-  HIP_OR(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
-  HIP_OR(hipStreamSynchronize(s->stream));
+  e = pull_states(s);
+  if (e != FOE_OK) return e;
   if (info_host) {
     info_host[0] = h.sums[0];
     info_host[1] = h.sums[1];
@@ -503,25 +692,25 @@ foe_status foe_last_timing(foe_solver* s, double* ms, int32_t* trial_launches) {
 foe_status foe_profile_trial(foe_solver* s, int32_t reps, double* ms_mean) {
   if (!s || reps < 1 || !ms_mean) return fail(FOE_EINVAL, "bad argument");
   if (!s->graph_big) return fail(FOE_EINVAL, "run foe_solve first");
-  HIP_OR(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
-  HIP_OR(hipStreamSynchronize(s->stream));
-  DevState saved = *s->st_host;
-  s->st_host->done = 0;
-  HIP_OR(hipMemcpyAsync(s->st, s->st_host, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
+  foe_status st = pull_states(s);
+  if (st != FOE_OK) return st;
+  std::vector<DevState> saved(s->st_host, s->st_host + s->n_img);
+  for (int i = 0; i < s->n_img; ++i) s->st_host[i].done = 0;
+  st = push_states(s);
+  if (st != FOE_OK) return st;
   std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
-  foe_status status = FOE_OK;
   for (auto& e : ev)
-    if (hipEventCreate(&e) != hipSuccess) status = fail(FOE_EDEVICE, "hipEventCreate failed");
+    if (hipEventCreate(&e) != hipSuccess) st = fail(FOE_EDEVICE, "hipEventCreate failed");
   const FusedArgs a = fused_args(s, MODE_TRIAL, s->fbuf, nullptr, nullptr);
   double total = 0.0;
-  if (status == FOE_OK) {
+  if (st == FOE_OK) {
     for (int r = 0; r < reps; ++r) {
       (void)hipEventRecord(ev[2 * r], s->stream);
       launch_fused(s, a, s->stream);
       (void)hipEventRecord(ev[2 * r + 1], s->stream);
     }
-    if (hipStreamSynchronize(s->stream) != hipSuccess) status = fail(FOE_EDEVICE, "trial launches failed");
-    for (int r = 0; r < reps && status == FOE_OK; ++r) {
+    if (hipStreamSynchronize(s->stream) != hipSuccess) st = fail(FOE_EDEVICE, "trial launches failed");
+    for (int r = 0; r < reps && st == FOE_OK; ++r) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
       total += ms;
@@ -529,11 +718,73 @@ foe_status foe_profile_trial(foe_solver* s, int32_t reps, double* ms_mean) {
   }
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
-  *s->st_host = saved;
-  HIP_OR(hipMemcpyAsync(s->st, s->st_host, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
+  std::copy(saved.begin(), saved.end(), s->st_host);
+  foe_status e2 = push_states(s);
   HIP_OR(hipStreamSynchronize(s->stream));
-  if (status == FOE_OK) *ms_mean = total / reps;
-  return status;
+  if (st == FOE_OK && e2 == FOE_OK) *ms_mean = total / reps;
+  return st != FOE_OK ? st : e2;
+}
+
+foe_status foe_autotune(foe_solver* s, const float* d_f, int32_t reps, int32_t* chosen) {
+  if (!s || !d_f || reps < 1) return fail(FOE_EINVAL, "bad argument");
+  const char* cache = std::getenv("FOE_TUNE_CACHE");
+  const std::string key = tune_key(s);
+  int best = -1;
+  if (cache) {
+    std::ifstream in(cache);
+    std::string k;
+    int c;
+    while (in >> k >> c)
+      if (k == key && c >= 0 && c < N_TILE_CFGS) best = c;
+  }
+  if (best < 0) {
+    bool bad = false;
+    foe_status st = init_from_f(s, d_f, nullptr, &bad);
+    if (st != FOE_OK) return st;
+    if (bad) return fail(FOE_EINPUT, "f has a non-finite or non-positive pixel");
+    double best_ms = 1e30;
+    hipEvent_t e0, e1;
+    HIP_OR(hipEventCreate(&e0));
+    HIP_OR(hipEventCreate(&e1));
+    for (int c = 0; c < N_TILE_CFGS; ++c) {
+      build_tiles(s, c);
+      st = upload_tiles(s);
+      if (st != FOE_OK) return st;
+      // gradient at x^0, then `reps` identical trials from the same state
+      launch_fused(s, fused_args(s, MODE_EVAL, s->fbuf, s->xr[0], s->gr[0]), s->stream);
+      launch_fused(s, fused_args(s, MODE_TRIAL, s->fbuf, nullptr, nullptr), s->stream);
+      HIP_OR(hipEventRecord(e0, s->stream));
+      for (int r = 0; r < reps; ++r) launch_fused(s, fused_args(s, MODE_TRIAL, s->fbuf, nullptr, nullptr), s->stream);
+      HIP_OR(hipEventRecord(e1, s->stream));
+      HIP_OR(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_OR(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (cache) {
+      std::ofstream o(cache, std::ios::app);
+      o << key << " " << best << "\n";
+    }
+  }
+  drop_graphs(s);
+  build_tiles(s, best);
+  foe_status st = upload_tiles(s);
+  if (st != FOE_OK) return st;
+  if (chosen) *chosen = best;
+  return FOE_OK;
+}
+
+foe_status foe_set_tile_config(foe_solver* s, int32_t cfg) {
+  if (!s || cfg < 0 || cfg >= N_TILE_CFGS) return fail(FOE_EINVAL, "bad tile configuration");
+  HIP_OR(hipStreamSynchronize(s->stream));
+  drop_graphs(s);
+  build_tiles(s, cfg);
+  return upload_tiles(s);
 }
 
 const char* foe_status_str(foe_status st) {

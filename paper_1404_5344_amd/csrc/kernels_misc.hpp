@@ -5,9 +5,13 @@
 namespace foe {
 
 // x^0 = x^{-1} = log u0 (log models) or u0 (IDIV), u0 = init or f.  Flags invalid input.
+// Grid: (blocks, images); block row blockIdx.y covers image blockIdx.y.
 __global__ void init_state_kernel(const float* __restrict__ f, const float* __restrict__ u0, float* x0, float* x1,
-                                  size_t n, int model, DevState* st) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                  const ImageDesc* images, int model, DevState* states) {
+  const ImageDesc im = images[blockIdx.y];
+  const size_t n = (size_t)im.off + (size_t)im.H * im.W;
+  DevState* st = states + blockIdx.y;
+  size_t i = (size_t)im.off + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool bad = false;
   for (; i < n; i += (size_t)gridDim.x * blockDim.x) {
     float fv = f[i];
@@ -21,8 +25,11 @@ __global__ void init_state_kernel(const float* __restrict__ f, const float* __re
 }
 
 // Validity check of caller-provided state (resumable entry point).
-__global__ void check_input_kernel(const float* __restrict__ f, size_t n, DevState* st) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void check_input_kernel(const float* __restrict__ f, const ImageDesc* images, DevState* states) {
+  const ImageDesc im = images[blockIdx.y];
+  const size_t n = (size_t)im.off + (size_t)im.H * im.W;
+  DevState* st = states + blockIdx.y;
+  size_t i = (size_t)im.off + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool bad = false;
   for (; i < n; i += (size_t)gridDim.x * blockDim.x) {
     float fv = f[i];
@@ -38,12 +45,17 @@ enum DecideMode { DECIDE_STEP = 0, DECIDE_INIT = 1, DECIDE_REPORT = 2 };
 // non-finite F(x+) or G(x+) fails;
 // on acceptance rotate the x and gradient rings and record the stats row; on rejection
 // L <- eta_up L.  FIXED mode always accepts.
-__global__ __launch_bounds__(256) void decide_kernel(DevState* st, const double* __restrict__ partials, int nblocks,
-                                                     Problem pb, double* stats, int mode) {
+// One block per image: block b reduces the partials of image b's tiles.
+__global__ __launch_bounds__(256) void decide_kernel(DevState* states, const double* __restrict__ partials,
+                                                     const ImageDesc* images, Problem pb, double* stats_all,
+                                                     int stats_rows, int mode) {
+  DevState* st = states + blockIdx.x;
+  double* stats = stats_all + (size_t)blockIdx.x * stats_rows * STAT_COLS;
+  const ImageDesc im = images[blockIdx.x];
   if (mode == DECIDE_STEP && st->done) return;
   __shared__ double red[256 / 64][5];
   double v[5] = {0, 0, 0, 0, 0};
-  for (int b = threadIdx.x; b < nblocks; b += 256)
+  for (int b = im.tile0 + threadIdx.x; b < im.tile0 + im.ntiles; b += 256)
 #pragma unroll
     for (int k = 0; k < 5; ++k) v[k] += partials[(size_t)b * PART_COLS + k];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -110,29 +122,35 @@ __global__ __launch_bounds__(256) void decide_kernel(DevState* st, const double*
   }
 }
 
-// u = e^{x^n} (log models) or x^n, from the ring slot the state names.
-__global__ void finalize_kernel(const DevState* st, const float* x0, const float* x1, const float* x2, float* u,
-                                size_t n, int model) {
-  const float* x = pick3(st->icur, (float*)x0, (float*)x1, (float*)x2);
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+// u = e^{x^n} (log models) or x^n, from the ring slot each image's state names.
+__global__ void finalize_kernel(const DevState* states, const float* x0, const float* x1, const float* x2, float* u,
+                                const ImageDesc* images, int model) {
+  const ImageDesc im = images[blockIdx.y];
+  const size_t n = (size_t)im.off + (size_t)im.H * im.W;
+  const float* x = pick3(states[blockIdx.y].icur, (float*)x0, (float*)x1, (float*)x2);
+  for (size_t i = (size_t)im.off + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
     u[i] = model == IDIV ? x[i] : expf(x[i]);
 }
 
 // Copy the ring slots the state names into caller buffers (resumable entry point).
-__global__ void export_state_kernel(const DevState* st, const float* x0, const float* x1, const float* x2,
-                                    float* xcur, float* xprev, size_t n) {
-  const float* c = pick3(st->icur, (float*)x0, (float*)x1, (float*)x2);
-  const float* p = pick3(st->iprev, (float*)x0, (float*)x1, (float*)x2);
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+__global__ void export_state_kernel(const DevState* states, const float* x0, const float* x1, const float* x2,
+                                    float* xcur, float* xprev, const ImageDesc* images) {
+  const ImageDesc im = images[blockIdx.y];
+  const size_t n = (size_t)im.off + (size_t)im.H * im.W;
+  const float* c = pick3(states[blockIdx.y].icur, (float*)x0, (float*)x1, (float*)x2);
+  const float* p = pick3(states[blockIdx.y].iprev, (float*)x0, (float*)x1, (float*)x2);
+  for (size_t i = (size_t)im.off + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
     xcur[i] = c[i];
     xprev[i] = p[i];
   }
 }
 
 __global__ void prox_probe_kernel(const float* __restrict__ xh, const float* __restrict__ f, float* out, size_t n,
-                                  float tau, Problem pb) {
+                                  float tau, Problem pb, float lam1, float lam2) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    out[i] = prox_pixel(xh[i], f[i], tau, pb.model, pb.lam1, pb.lam2, pb.newton_iters);
+    out[i] = prox_pixel(xh[i], f[i], tau, pb.model, lam1, lam2, pb.newton_iters);
 }
 
 }  // namespace foe

@@ -25,18 +25,19 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct FusedArgs {
   Problem pb;
-  const float* f;
-  float* xr0; float* xr1; float* xr2;   // x ring (TRIAL)
-  float* gr0; float* gr1;               // gradient ring (TRIAL)
-  const float* x_in;                    // EVAL input
-  float* g_out;                         // EVAL output
-  DevState* st;
+  const TileDesc* tiles;                // [gridDim.x]
+  const ImageDesc* images;
+  const float* f;                       // packed planes of all images
+  float* xr0; float* xr1; float* xr2;   // x ring (TRIAL), packed
+  float* gr0; float* gr1;               // gradient ring (TRIAL), packed
+  const float* x_in;                    // EVAL input, packed
+  float* g_out;                         // EVAL output, packed
+  DevState* st;                         // per-image states
   double* partials;                     // [gridDim.x][PART_COLS]
   const float* kf;                      // forward taps, flipped and chunk-transposed:
                                         //   kf[(c * KK + a * 7 + b) * NC + j] = k_{c*NC+j}[6-a][6-b]
   const float* ka;                      // adjoint taps: ka[i][a][b] = k_i[a][b]
   const float* theta;
-  int tiles_x;
   int mode;
 };
 
@@ -137,8 +138,10 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
   __shared__ float u6[H6 * W6];
   __shared__ __attribute__((aligned(16))) float zp[NC * PLANEP];
   __shared__ double red[(NT / 64) * 5];
-  __shared__ int act_off[NS];    // compacted fold slots: z-plane offset of the 7x7 window
-  __shared__ short act_slot[NS]; //                       and the slot id
+  __shared__ int act_off[NS];    // compacted fold slots: z-plane offset of the 7x7 window,
+  __shared__ short act_slot[NS]; //                       the slot id
+  __shared__ char act_rows[NS];  //                       and the window rows / columns that lie
+  __shared__ char act_cols[NS];  //                       inside the z plane (the rest is off the image)
   __shared__ int wave_cnt[NT / 64];
   // taps of the current chunk, read by broadcast LDS loads so that the FMAs take them from VGPRs
   // (a VALU FMA with an SGPR operand issues at half rate on gfx950)
@@ -148,8 +151,12 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
 
   const int tid = threadIdx.x;
   const Problem pb = a.pb;
-  const int H = pb.H, W = pb.W, bc = pb.bc, model = pb.model;
+  const TileDesc td = a.tiles[blockIdx.x];
+  const ImageDesc im = a.images[td.image];
+  const int H = im.H, W = im.W, bc = pb.bc, model = pb.model;
+  const float lam1 = im.lam1, lam2 = im.lam2;
   const bool logm = model != IDIV;
+  const int x0 = td.x0, y0 = td.y0;
 
   const float* xc;
   const float* xp = nullptr;
@@ -158,22 +165,19 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
   float* go;
   float alpha = 0.0f;
   if (a.mode == MODE_TRIAL) {
-    const DevState* st = a.st;
+    const DevState* st = a.st + td.image;
     if (st->done) return;
     alpha = (float)st->alpha;
-    xc = pick3(st->icur, a.xr0, a.xr1, a.xr2);
-    xp = pick3(st->iprev, a.xr0, a.xr1, a.xr2);
-    xo = pick3(st->icand, a.xr0, a.xr1, a.xr2);
-    gc = pick2(st->gcur, a.gr0, a.gr1);
-    go = pick2(st->gcand, a.gr0, a.gr1);
+    xc = pick3(st->icur, a.xr0, a.xr1, a.xr2) + im.off;
+    xp = pick3(st->iprev, a.xr0, a.xr1, a.xr2) + im.off;
+    xo = pick3(st->icand, a.xr0, a.xr1, a.xr2) + im.off;
+    gc = pick2(st->gcur, a.gr0, a.gr1) + im.off;
+    go = pick2(st->gcand, a.gr0, a.gr1) + im.off;
   } else {
-    xc = a.x_in;
-    go = a.g_out;
+    xc = a.x_in + im.off;
+    go = a.g_out + im.off;
   }
-  const float* __restrict__ f = a.f;
-
-  const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
-  const int x0 = tx * TW, y0 = ty * TH;
+  const float* __restrict__ f = a.f + im.off;
   const bool fold = bc == SYMMETRIC && (y0 < R || y0 + TH > H - R || x0 < R || x0 + TW > W - R);
 
   double accF = 0.0, accG = 0.0, accS1 = 0.0, accS2 = 0.0, accM = 0.0;
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
       if (a.mode == MODE_TRIAL) {
         float xv = xc[p], xpv = xp[p], gv = gc[p];
         float xh = xv - alpha * gv + pb.beta * (xv - xpv);
-        xn = prox_pixel(xh, fv, alpha, model, pb.lam1, pb.lam2, pb.newton_iters);
+        xn = prox_pixel(xh, fv, alpha, model, lam1, lam2, pb.newton_iters);
         uval = logm ? fast_exp(xn) : xn;
         if (own) {
           xo[p] = xn;
@@ -200,12 +204,12 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
           accS1 += (double)(gv * d);
           accS2 += (double)(d * d);
           accM += (double)(m * m);
-          accG += (double)data_term(xn, uval, fv, model, pb.lam1, pb.lam2);
+          accG += (double)data_term(xn, uval, fv, model, lam1, lam2);
         }
       } else {
         xn = xc[p];
         uval = logm ? fast_exp(xn) : xn;
-        if (own) accG += (double)data_term(xn, uval, fv, model, pb.lam1, pb.lam2);
+        if (own) accG += (double)data_term(xn, uval, fv, model, lam1, lam2);
       }
     }
     u6[idx] = uval;
@@ -217,13 +221,19 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
     float4* z4 = reinterpret_cast<float4*>(zp);
     for (int i = tid; i < NC * PLANEP / 4; i += NT) z4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     bool act[2];
-    int off[2];
+    int off[2], nrow[2], ncol[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       int s = tid + h * NT, ply, plx, qy, qx;
       act[h] = s < NS && slot_target<TW, TH>(s, x0, y0, H, W, ply, plx, qy, qx);
-      // window top-left (tile coords qy - y0, qx - x0) in z-plane coordinates
-      off[h] = act[h] ? (qy - y0 + ZR) * W3P + (qx - x0 + ZC) : 0;
+      // window top-left (tile coords qy - y0, qx - x0) in z-plane coordinates.  When the tile
+      // after this one holds fewer than 3 rows (columns), a mirrored sample lies up to 4 rows
+      // (columns) past the tile and its window reaches past the plane; those samples are off the
+      // image (zero), so the window is cut at the plane edge.
+      const int wr = qy - y0 + ZR, wc = qx - x0 + ZC;
+      off[h] = act[h] ? wr * W3P + wc : 0;
+      nrow[h] = min(KS, H3P - wr);
+      ncol[h] = min(KS, W3P - wc);
     }
     const int lane = tid & 63, wave = tid >> 6;
     int base = 0;
@@ -242,6 +252,8 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
       if (act[h]) {
         act_off[pos] = off[h];
         act_slot[pos] = (short)(tid + h * NT);
+        act_rows[pos] = (char)nrow[h];
+        act_cols[pos] = (char)ncol[h];
       }
       base += total;
       __syncthreads();
@@ -495,11 +507,15 @@ __global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
           const int m = lt + k * GT;
           if (m >= n_act) break;
           const float* zw = zplane + act_off[m];
+          const int nr = act_rows[m], nc = act_cols[m];
           float v = 0.0f;
 #pragma unroll
-          for (int ta = 0; ta < KS; ++ta)
+          for (int ta = 0; ta < KS; ++ta) {
+            if (ta >= nr) break;
 #pragma unroll
-            for (int tb = 0; tb < KS; ++tb) v = fmaf(kt[ta * KS + tb], zw[ta * W3P + tb], v);
+            for (int tb = 0; tb < KS; ++tb)
+              if (tb < nc) v = fmaf(kt[ta * KS + tb], zw[ta * W3P + tb], v);
+          }
           sacc[k] += v;
         }
       }

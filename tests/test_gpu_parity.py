@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 MODELS = [oracle.COMBINED, oracle.LOG, oracle.IDIV]
 BCS = [oracle.SYMMETRIC, oracle.ZERO, oracle.PERIODIC]
-SIZES = [(8, 8), (13, 21), (37, 64), (70, 45), (100, 131)]
+# ragged tails of every length mod 32, including tails of 1 and 2 (mirror samples past the next tile)
+SIZES = [(8, 8), (13, 21), (37, 64), (70, 45), (100, 131), (33, 257), (66, 34)]
 LAMS = {oracle.COMBINED: (358.0, 0.0104), oracle.LOG: (358.0, 0.0), oracle.IDIV: (10.0, 0.0)}
 
 
@@ -123,4 +124,24 @@ def test_random_filters_and_filter_counts(nf, engine):
     s = make_solver(H, W, bank, theta, engine=engine)
     g = s.eval_gradient(_gpu(x, dev)).cpu().numpy()
     assert rel_inf(g, oracle.grad_F(x, bank, theta)) <= 1e-4
+    s.close()
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(37, 64), (70, 45), (100, 131), (33, 257), (66, 98), (17, 18)])
+def test_gradient_tile_configs(shape, bc, cfg):
+    """Both tile configurations (32x32 and 32x16 output tiles) against the oracle."""
+    torch, dev = torch_dev()
+    H, W = shape
+    clean, f = speckled(H, W, seed=H * 7 + W)
+    bank, theta = bank_and_theta("random", seed=H)
+    x = state_for(oracle.COMBINED, f)
+    s = make_solver(H, W, bank, theta, boundary=bc)
+    s.set_tile_config(cfg)
+    g = s.eval_gradient(_gpu(x, dev)).cpu().numpy()
+    g_ora = oracle.grad_F(x, bank, theta, oracle.COMBINED, bc)
+    F, G = s.eval_energy(_gpu(x, dev), _gpu(f, dev))
+    assert rel_inf(g, g_ora) <= 1e-4, (shape, bc, cfg, rel_inf(g, g_ora))
+    assert abs(F - oracle.energy_F(x, bank, theta, oracle.COMBINED, bc)) <= 2e-6 * abs(F)
     s.close()
