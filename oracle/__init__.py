@@ -199,3 +199,41 @@ def ipiano(params: Params, f, bank, theta, iters: int, L0: float = 1.0, x_cur=No
     st = lib().ora_ipiano(ctypes.byref(pc), _p(f), _p(bank), _p(theta), len(theta), H, W, _p(x_cur), _p(x_prev),
                           ctypes.byref(Lc), iters, _p(stats))
     return Result(x_cur, x_prev, Lc.value, stats, st)
+
+
+# ---------------------------------------------------------------- warm-start network (cnn_oracle.c)
+def _cnn_lib():
+    L = lib()
+    if not getattr(L, "_cnn_ready", False):
+        L.ora_cnn_num_params.restype = ctypes.c_long
+        L.ora_cnn_loss_grad.argtypes = [_D, _D, _D, _I, _I, _I, _D]
+        L.ora_cnn_loss_grad.restype = ctypes.c_double
+        L.ora_cnn_forward.argtypes = [_D, _D, _I, _I, _D]
+        L._cnn_ready = True
+    return L
+
+
+CNN_LAYERS = [(1, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 1)]   # (in, out) channels
+CNN_SHIFT = 4.5
+
+
+def cnn_num_params() -> int:
+    return int(_cnn_lib().ora_cnn_num_params())
+
+
+def cnn_loss_grad(params, f, u_target, with_grad=True):
+    """Mean squared error of w0 = log f + net(log f - 4.5) against log u_target over a batch
+    [n, H, W], and its gradient with respect to the parameters (layout of cnn_oracle.c)."""
+    params = _f64(params); f = _f64(f); ut = _f64(u_target)
+    n, H, W = f.shape
+    g = np.zeros(params.size) if with_grad else None
+    loss = _cnn_lib().ora_cnn_loss_grad(_p(params), _p(f), _p(ut), n, H, W, _p(g) if with_grad else None)
+    return float(loss), g
+
+
+def cnn_forward(params, f):
+    params = _f64(params); f = _f64(f)
+    H, W = f.shape
+    w0 = np.empty_like(f)
+    _cnn_lib().ora_cnn_forward(_p(params), _p(f), H, W, _p(w0))
+    return w0
