@@ -182,6 +182,36 @@ foe_status foe_last_timing(foe_solver* s, double* ms, int32_t* trial_launches);
  * duration in milliseconds.  Requires a previous foe_solve / foe_solve_from. */
 foe_status foe_profile_trial(foe_solver* s, int32_t reps, double* ms_mean);
 
+/* ---- Warm-start network (an initialiser for the solve, outside the paper's method).
+ * w0 = log f + net(log f - 4.5): six 3x3 convolutions with zero "same" padding
+ * (1 -> 32, four times 32 -> 32, 32 -> 1), ReLU after the first five; the solve then starts
+ * from u0 = e^{w0} (foe_solve's d_init).  Parameters: per layer the weights
+ * W[co][ci][3][3] followed by the biases b[co], layers in order, foe_cnn_num_params() floats
+ * in total.  The handle keeps FP32 master parameters and their BF16 rounding; every
+ * convolution uses the BF16-rounded values with FP32 activations and accumulation.
+ * Batches are n images of one size H x W, packed [n][H][W] in device memory.  Activation
+ * workspace (13 planes of 32 n H W floats at most) is allocated on the first call of a larger
+ * size and kept.  Calls synchronise the handle's stream before returning.
+ * Errors: EINVAL (NULL or non-positive sizes), ENOMEM, EDEVICE. */
+typedef struct foe_cnn foe_cnn;
+int64_t foe_cnn_num_params(void);
+/* params_host: foe_cnn_num_params() floats, copied; Adam moments start at zero. */
+foe_status foe_cnn_create(const float* params_host, void* hip_stream, foe_cnn** out);
+foe_status foe_cnn_destroy(foe_cnn* c);
+/* Copies of the FP32 master parameters and of their BF16 rounding (each nullable). */
+foe_status foe_cnn_get_params(foe_cnn* c, float* master_host, float* bf16_host);
+/* d_u0 = e^{w0} for a batch d_f (> 0). */
+foe_status foe_cnn_infer(foe_cnn* c, const float* d_f, int32_t n, int32_t H, int32_t W, float* d_u0);
+/* loss = mean over the batch of (w0 - log u_t)^2 (double, nullable) and its gradient with
+ * respect to the BF16 parameters, copied to grad_host (nullable, parameter layout).  The
+ * weight gradients are reduced in a fixed order: the result is deterministic. */
+foe_status foe_cnn_loss_grad(foe_cnn* c, const float* d_f, const float* d_target_u, int32_t n, int32_t H, int32_t W,
+                             double* loss, float* grad_host);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr > 0) on the loss of the
+ * batch; the loss before the step goes to *loss (nullable). */
+foe_status foe_cnn_train_step(foe_cnn* c, const float* d_f, const float* d_target_u, int32_t n, int32_t H, int32_t W,
+                              double lr, double* loss);
+
 const char* foe_status_str(foe_status st);
 const char* foe_last_error(void);
 int32_t foe_abi_version(void);

@@ -237,3 +237,13 @@ def cnn_forward(params, f):
     w0 = np.empty_like(f)
     _cnn_lib().ora_cnn_forward(_p(params), _p(f), H, W, _p(w0))
     return w0
+
+
+def cnn_relu_margin(params, f) -> float:
+    """Smallest |pre-activation| of the ReLUs over a batch [n, H, W]."""
+    params = _f64(params); f = _f64(f)
+    n, H, W = f.shape
+    L = _cnn_lib()
+    L.ora_cnn_relu_margin.argtypes = [_D, _D, _I, _I, _I]
+    L.ora_cnn_relu_margin.restype = ctypes.c_double
+    return float(L.ora_cnn_relu_margin(_p(params), _p(f), n, H, W))

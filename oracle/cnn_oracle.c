@@ -159,3 +159,33 @@ void ora_cnn_forward(const double* params, const double* f, int H, int W, double
   forward(params, f, H, W, acts, w0);
   for (int l = 0; l <= CNN_LAYERS; ++l) free(acts[l]);
 }
+
+/* Smallest |pre-activation| over every ReLU of the network (layers 1-5) and every pixel of the
+ * batch: how close the forward pass comes to a ReLU decision that rounding could flip. */
+double ora_cnn_relu_margin(const double* params, const double* f, int nimg, int H, int W) {
+  size_t n = (size_t)H * W;
+  double* acts[CNN_LAYERS + 1];
+  for (int l = 0; l <= CNN_LAYERS; ++l) {
+    int c = l == 0 ? 1 : CNN_COUT[l - 1];
+    acts[l] = (double*)malloc(sizeof(double) * c * n);
+  }
+  double margin = INFINITY;
+  for (int im = 0; im < nimg; ++im) {
+    const double* fi = f + (size_t)im * n;
+    for (size_t p = 0; p < n; ++p) acts[0][p] = log(fi[p]) - CNN_SHIFT;
+    const double* prm = params;
+    for (int l = 0; l < CNN_LAYERS - 1; ++l) {
+      const double* w = prm;
+      const double* b = prm + CNN_COUT[l] * CNN_CIN[l] * 9;
+      conv3(acts[l], CNN_CIN[l], CNN_COUT[l], H, W, w, b, acts[l + 1]);
+      for (size_t q = 0; q < (size_t)CNN_COUT[l] * n; ++q) {
+        double z = acts[l + 1][q];
+        if (fabs(z) < margin) margin = fabs(z);
+        acts[l + 1][q] = z > 0.0 ? z : 0.0;
+      }
+      prm = b + CNN_COUT[l];
+    }
+  }
+  for (int l = 0; l <= CNN_LAYERS; ++l) free(acts[l]);
+  return margin;
+}

@@ -77,6 +77,14 @@ def _load():
     L.foe_batch_solve.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(Summary), _DP]
     L.foe_autotune.argtypes = [_VP, _VP, ctypes.c_int32, _IP]
     L.foe_set_tile_config.argtypes = [_VP, ctypes.c_int32]
+    L.foe_cnn_num_params.restype = ctypes.c_int64
+    L.foe_cnn_create.argtypes = [_VP, _VP, ctypes.POINTER(_VP)]
+    L.foe_cnn_destroy.argtypes = [_VP]
+    L.foe_cnn_get_params.argtypes = [_VP, _VP, _VP]
+    L.foe_cnn_infer.argtypes = [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP]
+    L.foe_cnn_loss_grad.argtypes = [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _DP, _VP]
+    L.foe_cnn_train_step.argtypes = [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                     _DP]
     L.foe_status_str.argtypes = [ctypes.c_int]
     L.foe_status_str.restype = ctypes.c_char_p
     L.foe_last_error.argtypes = []
@@ -84,7 +92,8 @@ def _load():
     L.foe_abi_version.restype = ctypes.c_int32
     for name in ("foe_create", "foe_destroy", "foe_solve", "foe_solve_from", "foe_eval_gradient", "foe_eval_energy",
                  "foe_eval_prox", "foe_step", "foe_last_timing", "foe_profile_trial", "foe_batch_create",
-                 "foe_batch_layout", "foe_batch_solve", "foe_autotune", "foe_set_tile_config"):
+                 "foe_batch_layout", "foe_batch_solve", "foe_autotune", "foe_set_tile_config", "foe_cnn_create",
+                 "foe_cnn_destroy", "foe_cnn_get_params", "foe_cnn_infer", "foe_cnn_loss_grad", "foe_cnn_train_step"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -308,3 +317,86 @@ class BatchSolver(Solver):
         _check(st, (OK, ELINESEARCH, ENONFINITE) if allow_failure else (OK,))
         summaries = [sums[i].as_dict() for i in range(n)]
         return out, summaries, [stats[i, :summaries[i]["iters_done"]].copy() for i in range(n)], st
+
+
+CNN_LAYERS = [(1, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 1)]   # (in, out) channels, 3x3 taps
+
+
+def cnn_num_params() -> int:
+    return int(lib.foe_cnn_num_params())
+
+
+def cnn_init_params(seed: int) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / (9 c_in))), zero biases; the last layer is scaled by 0.1
+    so that the untrained network starts near w0 = log f."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for l, (ci, co) in enumerate(CNN_LAYERS):
+        std = np.sqrt(2.0 / (9 * ci)) * (0.1 if l == len(CNN_LAYERS) - 1 else 1.0)
+        parts += [rng.standard_normal(co * ci * 9) * std, np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+class WarmStartNet:
+    """The warm-start network on the GPU.  Batches are float32 CUDA tensors [n, H, W]."""
+
+    def __init__(self, params, stream=None):
+        torch = _torch()
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        if p.size != cnn_num_params():
+            raise ValueError(f"expected {cnn_num_params()} parameters, got {p.size}")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _VP()
+        _check(lib.foe_cnn_create(p.ctypes.data_as(_VP), _VP(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.foe_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_in(self):
+        torch = _torch()
+        if self.stream != torch.cuda.current_stream():
+            self.stream.wait_stream(torch.cuda.current_stream())
+
+    def params(self):
+        """(FP32 master parameters, their BF16 rounding) as NumPy float32 arrays."""
+        m = np.zeros(cnn_num_params(), np.float32)
+        q = np.zeros(cnn_num_params(), np.float32)
+        _check(lib.foe_cnn_get_params(self._h, m.ctypes.data_as(_VP), q.ctypes.data_as(_VP)))
+        return m, q
+
+    def infer(self, f, out=None):
+        torch = _torch()
+        self._sync_in()
+        n, H, W = f.shape
+        if out is None:
+            out = torch.empty_like(f)
+        _check(lib.foe_cnn_infer(self._h, _dev_ptr(f, None, "f"), n, H, W, _dev_ptr(out, f.shape, "out")))
+        return out
+
+    def loss_grad(self, f, u_target):
+        self._sync_in()
+        n, H, W = f.shape
+        loss = ctypes.c_double()
+        g = np.zeros(cnn_num_params(), np.float32)
+        _check(lib.foe_cnn_loss_grad(self._h, _dev_ptr(f, None, "f"), _dev_ptr(u_target, f.shape, "u_target"), n, H,
+                                     W, ctypes.byref(loss), g.ctypes.data_as(_VP)))
+        return loss.value, g
+
+    def train_step(self, f, u_target, lr):
+        self._sync_in()
+        n, H, W = f.shape
+        loss = ctypes.c_double()
+        _check(lib.foe_cnn_train_step(self._h, _dev_ptr(f, None, "f"), _dev_ptr(u_target, f.shape, "u_target"), n,
+                                      H, W, float(lr), ctypes.byref(loss)))
+        return loss.value

@@ -11,6 +11,8 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libfoe.so")
 ROOT = os.path.dirname(HERE)
 
+SOURCES = ["foe_lib.hip", "cnn.hip"]
+
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere in the library
@@ -22,7 +24,7 @@ HIPCC_FLAGS = [
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + HIPCC_FLAGS + (extra or []) + ["-o", tmp, os.path.join(CSRC, "foe_lib.hip")]
+    cmd = ["hipcc"] + HIPCC_FLAGS + (extra or []) + ["-o", tmp] + [os.path.join(CSRC, n) for n in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

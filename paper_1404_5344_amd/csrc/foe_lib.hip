@@ -70,6 +70,9 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 }  // namespace
 
+// Lets the other translation units of the library report through foe_last_error().
+void foe_internal_set_error(const std::string& msg) { g_last_error = msg; }
+
 struct foe_solver {
   foe_params p{};
   Problem pb{};

@@ -1,0 +1,167 @@
+"""Warm start of the iPiano solve by a small learned network (an extension; the paper always
+starts from x^0 = log f).
+
+Pipeline, every step on the GPU through the library's own kernels:
+  1. training pairs: seeded speckled 128 x 128 images (looks alternating 1 / 4) and the plain
+     solver's 300-iteration output for each, computed by the batched solver;
+  2. training: Adam on the mean squared log-amplitude error, forward and backward passes by the
+     network kernels (``WarmStartNet``);
+  3. inference: u0 = network(f), then a short iPiano run from u0; when that run ends at an energy
+     more than 0.5 % above the plain run's, the plain run is the answer (fallback).
+
+Run as a script to train a network and write its parameters:
+    python -m paper_1404_5344_amd.warmstart --images 20000 --epochs 8 --out weights.npy
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+from . import BatchSolver, WarmStartNet, cnn_init_params, default_params
+
+FALLBACK_RATIO = 1.005      # warm-start energy above this multiple of the plain energy -> fallback
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_cnn.npy")
+
+
+def _train_image(i):
+    import synth
+    p = synth.config5_train(i)
+    return p.f, p.looks
+
+
+def training_inputs(n_images: int, workers: int = 8):
+    """Noisy 128 x 128 training images (float32 [n, 128, 128]) and their looks, from the seeded
+    generator; generated in host worker processes."""
+    if workers <= 1:
+        res = [_train_image(i) for i in range(n_images)]
+    else:
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            res = list(ex.map(_train_image, range(n_images), chunksize=64))
+    return np.stack([r[0] for r in res]), [r[1] for r in res]
+
+
+def plain_targets(f, looks, bank, theta, iters: int = 300, batch: int = 256):
+    """The plain solver's output (x^0 = log f, `iters` iterations) for every image of f
+    (CUDA tensor [n, H, W]), solved `batch` images per batched launch."""
+    import torch
+    n, H, W = f.shape
+    out = torch.empty_like(f)
+    solvers = {}
+    for s in range(0, n, batch):
+        m = min(batch, n - s)
+        key = (m, tuple(looks[s:s + m]))
+        if key not in solvers:
+            p = default_params(0, 0, max_iters=iters)
+            solvers[key] = BatchSolver(p, [(H, W)] * m, list(looks[s:s + m]), bank, theta)
+        b = solvers[key]
+        u, _, _, _ = b.solve(f[s:s + m].reshape(-1).contiguous())
+        out[s:s + m] = u.reshape(m, H, W)
+    for b in solvers.values():
+        b.close()
+    return out
+
+
+def train(net: WarmStartNet, f, u, epochs: int, batch: int = 32, lr: float = 1e-3, seed: int = 0,
+          lr_final: float = 1e-4, log=print):
+    """Adam over shuffled mini-batches; the learning rate decays geometrically from lr to
+    lr_final over the run.  Returns the mean loss of each epoch."""
+    import torch
+    n = f.shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    steps = epochs * (n // batch)
+    k = 0
+    losses = []
+    for e in range(epochs):
+        order = torch.from_numpy(rng.permutation(n)).to(f.device)
+        tot = 0.0
+        t0 = time.perf_counter()
+        for s in range(n // batch):
+            idx = order[s * batch:(s + 1) * batch]
+            rate = lr * (lr_final / lr) ** (k / max(steps - 1, 1))
+            tot += net.train_step(f[idx].contiguous(), u[idx].contiguous(), rate)
+            k += 1
+        losses.append(tot / (n // batch))
+        if log:
+            log(f"epoch {e}: loss {losses[-1]:.5f} ({time.perf_counter() - t0:.1f} s)")
+    return losses
+
+
+def warm_solve(batch: BatchSolver, net: WarmStartNet, f):
+    """u0 = network(f) for every image of a batch of equal-size images (CUDA tensor [n, H, W]),
+    then the batch solver's iterations from u0.  Returns (u, summaries, u0)."""
+    u0 = net.infer(f)
+    u, sums, _, _ = batch.solve(f.reshape(-1).contiguous(), init=u0.reshape(-1).contiguous())
+    return u.reshape(f.shape), sums, u0
+
+
+def evaluate(net: WarmStartNet, f, looks, bank, theta, iters_warm: int = 40, iters_plain: int = 300):
+    """Held-out evaluation of a batch of equal-size images: the plain run (x^0 = log f,
+    iters_plain iterations), the same number of iterations as the warm start but from log f, and
+    the warm start (network, then iters_warm iterations) with its energy fallback.  Returns
+    (u_plain, u_short, u_warm_or_fallback, records) with per-image energies and fallback flags."""
+    n, H, W = f.shape
+    looks = list(looks)
+    sizes = [(H, W)] * n
+    bp = BatchSolver(default_params(0, 0, max_iters=iters_plain), sizes, looks, bank, theta)
+    bs = BatchSolver(default_params(0, 0, max_iters=iters_warm), sizes, looks, bank, theta)
+    fp = f.reshape(-1).contiguous()
+    u_plain, s_plain, _, _ = bp.solve(fp)
+    u_short, s_short, _, _ = bs.solve(fp)
+    u_warm, s_warm, _ = warm_solve(bs, net, f)
+    u_plain, u_short = u_plain.reshape(f.shape), u_short.reshape(f.shape)
+    records = []
+    out = u_warm.clone()
+    for i in range(n):
+        fb = s_warm[i]["H"] > FALLBACK_RATIO * s_plain[i]["H"]
+        if fb:
+            out[i] = u_plain[i]
+        records.append(dict(H_plain=s_plain[i]["H"], H_short=s_short[i]["H"], H_warm=s_warm[i]["H"], fallback=fb))
+    bp.close()
+    bs.close()
+    return u_plain, u_short, out, records
+
+
+def save(net: WarmStartNet, path: str = WEIGHTS):
+    master, _ = net.params()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.save(path, master)
+
+
+def load(path: str = WEIGHTS, stream=None) -> WarmStartNet:
+    return WarmStartNet(np.load(path), stream=stream)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--images", type=int, default=20000)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=WEIGHTS)
+    a = ap.parse_args()
+    import synth
+    t0 = time.perf_counter()
+    f_np, looks = training_inputs(a.images)
+    print(f"generated {a.images} training images in {time.perf_counter() - t0:.1f} s", flush=True)
+    import torch
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(f_np).to(dev)
+    t0 = time.perf_counter()
+    u = plain_targets(f, looks, synth.dct_bank(), synth.theta_weights(5))
+    torch.cuda.synchronize()
+    print(f"plain 300-iteration targets in {time.perf_counter() - t0:.1f} s", flush=True)
+    net = WarmStartNet(cnn_init_params(a.seed))
+    t0 = time.perf_counter()
+    train(net, f, u, a.epochs, a.batch, a.lr, a.seed, log=lambda m: print(m, flush=True))
+    print(f"trained in {time.perf_counter() - t0:.1f} s", flush=True)
+    save(net, a.out)
+    print(f"wrote {a.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

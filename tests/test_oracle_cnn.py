@@ -56,3 +56,19 @@ def test_gradient_finite_differences():
     d = r.standard_normal(p.size)
     fd = (oracle.cnn_loss_grad(p + h * d, f, ut, False)[0] - oracle.cnn_loss_grad(p - h * d, f, ut, False)[0]) / (2 * h)
     assert abs(fd - g @ d) <= 1e-6 * abs(g @ d)
+
+
+def test_relu_margin_special_cases():
+    # zero weights: every pre-activation equals its layer's bias
+    import oracle
+    p = np.zeros(oracle.cnn_num_params())
+    off = 0
+    biases = [0.5, 0.7, 0.3, 0.9, 0.6, 0.2]
+    for l, (ci, co) in enumerate(oracle.CNN_LAYERS):
+        off += co * ci * 9
+        p[off:off + co] = biases[l]
+        off += co
+    f = np.full((1, 5, 6), 3.0)
+    assert oracle.cnn_relu_margin(p, f) == 0.3      # layers 1-5 only; the output layer has no ReLU
+    p[oracle.CNN_LAYERS[0][1] * 9:oracle.CNN_LAYERS[0][1] * 10] = -0.05
+    assert oracle.cnn_relu_margin(p, f) == 0.05
