@@ -181,35 +181,66 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(const float* __restrict__ 
   if (threadIdx.x < C) pout[C * C * 9 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
-// Weight gradient of a small layer (1 -> 32 or 32 -> 1): one thread per parameter, summing over
-// the pixels of one image in a fixed order.  Grid: (ceil(np / 256), images); partial [images][np].
+// Weight gradient of a small layer (1 -> 32 or 32 -> 1), partial over a range of tiles: the
+// input tile (with its 1-pixel halo) and the output-gradient tile are staged in LDS, and each
+// thread sums one or two parameters over the staged pixels in a fixed order.
+// Grid: (tile groups, images); partial: [gridDim.y][gridDim.x][CO*CI*9 + CO].
 template <int CI, int CO>
 __global__ __launch_bounds__(256) void wgrad_small_kernel(const float* __restrict__ in, const float* __restrict__ dout,
-                                                          float* __restrict__ partial, int H, int W) {
-  constexpr int NP = CO * CI * 9 + CO;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= NP) return;
+                                                          float* __restrict__ partial, int H, int W,
+                                                          int tiles_per_block) {
+  constexpr int NP = CO * CI * 9 + CO, PER = (NP + 255) / 256;
+  __shared__ float sin_[CI][TS + 2][TS + 2];
+  __shared__ float sd[CO][TS][TS];
   const int n = blockIdx.y;
   const size_t plane = (size_t)H * W;
+  const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TS - 1) / TS, ntiles = tiles_x * tiles_y;
   const float* inb = in + (size_t)n * CI * plane;
   const float* db = dout + (size_t)n * CO * plane;
-  float s = 0.0f;
-  if (i < CO * CI * 9) {
-    const int co = i / (CI * 9), ci = (i / 9) % CI, t = i % 9, dy = t / 3 - 1, dx = t % 3 - 1;
-    for (int y = 0; y < H; ++y) {
-      const int yy = y + dy;
-      if (yy < 0 || yy >= H) continue;
-      for (int x = 0; x < W; ++x) {
-        const int xx = x + dx;
-        if (xx < 0 || xx >= W) continue;
-        s = fmaf(db[co * plane + (size_t)y * W + x], inb[ci * plane + (size_t)yy * W + xx], s);
+  float acc[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) acc[k] = 0.0f;
+  for (int tt = 0; tt < tiles_per_block; ++tt) {
+    const int tile = blockIdx.x * tiles_per_block + tt;
+    if (tile >= ntiles) break;
+    const int x0 = (tile % tiles_x) * TS, y0 = (tile / tiles_x) * TS;
+    for (int i = threadIdx.x; i < CI * (TS + 2) * (TS + 2); i += 256) {
+      const int ci = i / ((TS + 2) * (TS + 2)), r = (i / (TS + 2)) % (TS + 2), c = i % (TS + 2);
+      const int y = y0 + r - 1, x = x0 + c - 1;
+      sin_[ci][r][c] = (y >= 0 && y < H && x >= 0 && x < W) ? inb[ci * plane + (size_t)y * W + x] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < CO * TS * TS; i += 256) {
+      const int co = i / (TS * TS), r = (i / TS) % TS, c = i % TS;
+      const int y = y0 + r, x = x0 + c;
+      sd[co][r][c] = (y < H && x < W) ? db[co * plane + (size_t)y * W + x] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < CO * CI * 9) {
+        const int co = i / (CI * 9), ci = (i / 9) % CI, t = i % 9, dy = t / 3, dx = t % 3;
+        float s = 0.0f;
+        for (int r = 0; r < TS; ++r)
+#pragma unroll 4
+          for (int c = 0; c < TS; ++c) s = fmaf(sd[co][r][c], sin_[ci][r + dy][c + dx], s);
+        acc[k] += s;
+      } else if (i < NP) {
+        const int co = i - CO * CI * 9;
+        float s = 0.0f;
+        for (int r = 0; r < TS; ++r)
+          for (int c = 0; c < TS; ++c) s += sd[co][r][c];
+        acc[k] += s;
       }
     }
-  } else {
-    const int co = i - CO * CI * 9;
-    for (size_t p = 0; p < plane; ++p) s += db[co * plane + p];
+    __syncthreads();
   }
-  partial[(size_t)n * NP + i] = s;
+  float* pout = partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NP;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < NP) pout[i] = acc[k];
+  }
 }
 
 // grad[i] = sum_b partial[b][i] in increasing b.
@@ -420,11 +451,11 @@ foe_status loss_grad(foe_cnn* c, const float* d_f, const float* d_ut, int n, int
       wgrad32_kernel<<<dim3(groups, n), 256, 0, c->stream>>>(c->act[l], dcur, c->partial, H, W, WG_TILES);
       reduce_partials_kernel<<<(np + 255) / 256, 256, 0, c->stream>>>(c->partial, groups * n, np, g);
     } else if (l == 0) {
-      wgrad_small_kernel<1, 32><<<dim3((np + 255) / 256, n), 256, 0, c->stream>>>(c->act[0], dcur, c->partial, H, W);
-      reduce_partials_kernel<<<(np + 255) / 256, 256, 0, c->stream>>>(c->partial, n, np, g);
+      wgrad_small_kernel<1, 32><<<dim3(groups, n), 256, 0, c->stream>>>(c->act[0], dcur, c->partial, H, W, WG_TILES);
+      reduce_partials_kernel<<<(np + 255) / 256, 256, 0, c->stream>>>(c->partial, groups * n, np, g);
     } else {
-      wgrad_small_kernel<32, 1><<<dim3((np + 255) / 256, n), 256, 0, c->stream>>>(c->act[l], dcur, c->partial, H, W);
-      reduce_partials_kernel<<<(np + 255) / 256, 256, 0, c->stream>>>(c->partial, n, np, g);
+      wgrad_small_kernel<32, 1><<<dim3(groups, n), 256, 0, c->stream>>>(c->act[l], dcur, c->partial, H, W, WG_TILES);
+      reduce_partials_kernel<<<(np + 255) / 256, 256, 0, c->stream>>>(c->partial, groups * n, np, g);
     }
     if (l == 0) break;
     launch_conv(c, l, true, dcur, dnext, c->act[l], n, H, W);

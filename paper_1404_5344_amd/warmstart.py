@@ -9,8 +9,9 @@ Pipeline, every step on the GPU through the library's own kernels:
   3. inference: u0 = network(f), then a short iPiano run from u0; when that run ends at an energy
      more than 0.5 % above the plain run's, the plain run is the answer (fallback).
 
-Run as a script to train a network and write its parameters:
+Run as a script to train a network and write its parameters, or to evaluate saved parameters:
     python -m paper_1404_5344_amd.warmstart --images 20000 --epochs 8 --out weights.npy
+    python -m paper_1404_5344_amd.warmstart --evaluate 256 --out weights.npy
 """
 from __future__ import annotations
 
@@ -90,10 +91,20 @@ def train(net: WarmStartNet, f, u, epochs: int, batch: int = 32, lr: float = 1e-
     return losses
 
 
+def infer(net: WarmStartNet, f, chunk: int = 16):
+    """u0 = network(f) for a batch [n, H, W], `chunk` images per call (the network keeps the
+    activations of one call: 162 planes per image)."""
+    import torch
+    u0 = torch.empty_like(f)
+    for s in range(0, f.shape[0], chunk):
+        net.infer(f[s:s + chunk], out=u0[s:s + chunk])
+    return u0
+
+
 def warm_solve(batch: BatchSolver, net: WarmStartNet, f):
     """u0 = network(f) for every image of a batch of equal-size images (CUDA tensor [n, H, W]),
     then the batch solver's iterations from u0.  Returns (u, summaries, u0)."""
-    u0 = net.infer(f)
+    u0 = infer(net, f)
     u, sums, _, _ = batch.solve(f.reshape(-1).contiguous(), init=u0.reshape(-1).contiguous())
     return u.reshape(f.shape), sums, u0
 
@@ -135,8 +146,51 @@ def load(path: str = WEIGHTS, stream=None) -> WarmStartNet:
     return WarmStartNet(np.load(path), stream=stream)
 
 
+def _eval_image(i):
+    import synth
+    p = synth.config5_eval(i)
+    return p.f, p.clean, p.looks
+
+
+def held_out(n_images: int, workers: int = 8):
+    """Held-out 512 x 512 evaluation images (seed space disjoint from training): noisy f
+    [n, 512, 512] float32, clean [n, 512, 512] float64, looks."""
+    if workers <= 1:
+        res = [_eval_image(i) for i in range(n_images)]
+    else:
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            res = list(ex.map(_eval_image, range(n_images)))
+    return np.stack([r[0] for r in res]), np.stack([r[1] for r in res]), [r[2] for r in res]
+
+
+def report(n_images: int, path: str = WEIGHTS, iters_warm: int = 40, iters_plain: int = 300) -> dict:
+    """Held-out evaluation: PSNR and energy of the warm start (with fallback) against the plain
+    run and against the same iteration count from log f."""
+    import json
+    import synth
+    import torch
+    f_np, clean, looks = held_out(n_images)
+    f = torch.from_numpy(f_np).to("cuda:0")
+    net = load(path)
+    u_plain, u_short, u_warm, rec = evaluate(net, f, looks, synth.dct_bank(), synth.theta_weights(5), iters_warm,
+                                             iters_plain)
+    ps = lambda u: np.array([synth.psnr(u[i].cpu().numpy(), clean[i]) for i in range(n_images)])
+    p_plain, p_short, p_warm = ps(u_plain), ps(u_short), ps(u_warm)
+    gap = np.array([r["H_warm"] / r["H_plain"] - 1.0 for r in rec])
+    out = dict(images=n_images, iters_warm=iters_warm, iters_plain=iters_plain,
+               psnr_noisy=float(np.mean([synth.psnr(f_np[i], clean[i]) for i in range(n_images)])),
+               psnr_plain=float(p_plain.mean()), psnr_same_iters_from_log_f=float(p_short.mean()),
+               psnr_warm=float(p_warm.mean()), psnr_warm_minus_plain_min=float((p_warm - p_plain).min()),
+               energy_gap_mean=float(gap.mean()), energy_gap_max=float(gap.max()),
+               fallback_rate=float(np.mean([r["fallback"] for r in rec])))
+    net.close()
+    print(json.dumps(out), flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--evaluate", type=int, default=0, help="evaluate the saved network on this many held-out images")
     ap.add_argument("--images", type=int, default=20000)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch", type=int, default=32)
@@ -144,6 +198,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=WEIGHTS)
     a = ap.parse_args()
+    if a.evaluate:
+        report(a.evaluate, a.out)
+        return
     import synth
     t0 = time.perf_counter()
     f_np, looks = training_inputs(a.images)
