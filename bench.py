@@ -1,18 +1,26 @@
 """Throughput of the iPiano-FoE despeckling hot path on one MI355X.
 
-One step = one full solve of the 512x512 single-look workload (init, 300 iPiano
-iterations with backtracking, output) on synthetic input resident in HBM.
-Prints one JSON line:
-  value      Mpixel-iterations/s = H*W*accepted_iterations / wall time per step
-  roofline   the fused trial kernel against the FP32 peak (algorithmic flops per launch /
-             its mean launch duration from per-launch HIP event pairs)
+One step = one full solve of the 512x512 single-look workload (init, 300 iPiano iterations with
+backtracking, output) on synthetic input resident in HBM.  Prints one JSON line:
+  value         Mpixel-iterations/s = H * W * accepted iterations / wall time per step
+  roofline      the fused trial kernel: algorithmic flops per launch / its mean launch duration
+                (per-launch HIP event pairs on the solver stream), against the FP32 peak; traffic =
+                HBM bytes per launch from the committed hardware-counter summary when it was taken
+                on the current kernel sources, else null
   cpu_baseline  the FP64 oracle on the host cores over a bounded sample of the same workload
+  forms         time-to-PSNR of the batched, BF16 and warm-started forms against the plain FP32
+                solver on their own workloads (the wall time to reach the plain run's final PSNR
+                minus 0.01 dB, or 0.05 dB for BF16; the crossing iteration is found with a PSNR probe
+                and a separate run of exactly that many iterations is timed)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
+import re
 import sys
 import time
 
@@ -22,13 +30,36 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "Mpixel-iters/s iPiano-FoE on 1 GPU; time-to-PSNR vs plain FP32; roofline %"
-PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 (vector and matrix)
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 peak, vector and matrix cores alike
 NF, KK = 48, 49
 FLOP_PER_PX_TRIAL = 2 * 2 * NF * KK   # forward bank on x+ and adjoint bank, one FMA = 2 flop
+KERNEL_SOURCES = ["common.hpp", "device_math.hpp", "kernels_trial.hpp"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "foe_trial_kernel_512x512_hbm_traffic.md")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for n in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1404_5344_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the trial kernel from the committed counter summary, or None when
+    the summary is missing or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    text = open(TRAFFIC_SUMMARY).read()
+    m_hash = re.search(r"kernel source hash:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"HBM bytes per launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
 
 
 def cpu_baseline(pr, bank, theta, seconds_target=15.0):
@@ -44,10 +75,235 @@ def cpu_baseline(pr, bank, theta, seconds_target=15.0):
     r = oracle.ipiano(p, pr.f, bank, theta, iters, L0=1.0)
     dt = time.perf_counter() - t
     n_acc = int(r.stats.shape[0])
-    return {"value": H * W * n_acc / dt / 1e6, "unit": "Mpixel-iters/s", "cores": oracle.get_threads(),
+    return {"value": round(H * W * n_acc / dt / 1e6, 4), "unit": "Mpixel-iters/s", "cores": oracle.get_threads(),
             "kind": "oracle",
             "sample": f"FP64 oracle, same 512x512 input, first {n_acc} iterations from x0 = log f "
                       f"({int(r.stats[:, 4].sum())} trials), {dt:.1f} s"}
+
+
+# ------------------------------------------------------------------------------------ forms
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _wall(fn, reps=3):
+    """Median wall time of fn() over reps runs (after one untimed run), GPU synchronised."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        _sync()
+        t = time.perf_counter()
+        fn()
+        _sync()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts))
+
+
+def _psnr_t(u, clean_t, peak):
+    import torch
+    mse = torch.mean((u.double() - clean_t) ** 2).item()
+    return 10.0 * math.log10(peak * peak / mse)
+
+
+def _crossing(traj, target):
+    hit = np.nonzero(np.asarray(traj) >= target)[0]
+    return int(hit[0]) if hit.size else None
+
+
+def _probe(solver, f, x0, clean_t, peak, iters, exp=True):
+    """PSNR after 0..iters iterations from x^0 = x^{-1} = x0 (single-image solver)."""
+    import torch
+    x, xp, L = x0.clone(), x0.clone(), 1.0
+    out = [_psnr_t(torch.exp(x) if exp else x, clean_t, peak)]
+    for _ in range(iters):
+        L, _, _ = solver.solve_from(f, x, xp, L, 1)
+        out.append(_psnr_t(torch.exp(x), clean_t, peak))
+    return out
+
+
+def _run_from(solver, f, x0, k):
+    """Closure running exactly k iterations from x0 (state copies made outside the timed call)."""
+    state = {}
+
+    def prep():
+        state["x"], state["xp"] = x0.clone(), x0.clone()
+
+    def run():
+        if k > 0:
+            solver.solve_from(f, state["x"], state["xp"], 1.0, k)
+    return prep, run
+
+
+def _wall_prepped(prep, run, reps=3):
+    prep()
+    run()
+    ts = []
+    for _ in range(reps):
+        prep()
+        _sync()
+        t = time.perf_counter()
+        run()
+        _sync()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts))
+
+
+def form_bf16(dev):
+    """BF16 filter bank on the first 2048 x 2048 SAR-like tile against the FP32 solve."""
+    import torch
+    import paper_1404_5344_amd as foe
+    import synth
+    pr = synth.config4(0)
+    bank, theta = synth.dct_bank(), synth.theta_weights(4)
+    f = torch.from_numpy(pr.f).to(dev)
+    clean = torch.from_numpy(pr.clean).to(dev)
+    x0 = torch.log(f)
+    res = {}
+    solvers = {}
+    for name, kw in (("fp32", {}), ("bf16", dict(precision=1, engine=2))):
+        p = foe.default_params(2048, 2048, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=300, **kw)
+        solvers[name] = foe.Solver(p, bank, theta)
+        res[name] = _probe(solvers[name], f, x0, clean, pr.peak, 300)
+    target = res["fp32"][-1] - 0.05
+    out = {"workload": "2048x2048 SAR-like tile 0, L=1, 300 iterations", "tol_db": 0.05,
+           "psnr_final_fp32": round(res["fp32"][-1], 4), "psnr_final_bf16": round(res["bf16"][-1], 4)}
+    for name in ("fp32", "bf16"):
+        k = _crossing(res[name], target)
+        out[f"reached_{name}"] = k is not None
+        k = 300 if k is None else k
+        prep, run = _run_from(solvers[name], f, x0, k)
+        out[f"iters_{name}"] = k
+        out[f"seconds_{name}"] = round(_wall_prepped(prep, run), 5)
+        # throughput of the full 300 iterations in this precision
+        prep, run = _run_from(solvers[name], f, x0, 300)
+        t300 = _wall_prepped(prep, run, reps=2)
+        out[f"mpix_it_s_{name}"] = round(2048 * 2048 * 300 / t300 / 1e6, 1)
+    out["speedup"] = round(out["seconds_fp32"] / out["seconds_bf16"], 3)
+    for s in solvers.values():
+        s.close()
+    return out
+
+
+def form_batched(dev, n_images=64):
+    """64 uneven images in one batched solve against one single-image solve per image."""
+    import torch
+    import paper_1404_5344_amd as foe
+    import synth
+    sizes = synth.config3_sizes(n_images)
+    probs = [synth.config3_image(i, H, W, L) for i, (H, W, L) in enumerate(sizes)]
+    bank, theta = synth.dct_bank(), synth.theta_weights(3)
+    hw = [(H, W) for H, W, _ in sizes]
+    looks = [L for _, _, L in sizes]
+    b = foe.BatchSolver(foe.default_params(0, 0, max_iters=300), hw, looks, bank, theta)
+    b.autotune(b.pack([torch.from_numpy(p.f) for p in probs]).to(dev), reps=3)
+    f = b.pack([torch.from_numpy(p.f) for p in probs]).to(dev)
+    clean = b.pack([torch.from_numpy(p.clean) for p in probs]).to(dev).double()
+    offs = torch.tensor(b.offsets, device=dev)
+    npx = (offs[1:] - offs[:-1]).double()
+
+    def psnrs(x):
+        d2 = (torch.exp(x).double() - clean) ** 2
+        cs = torch.cat([torch.zeros(1, dtype=torch.float64, device=dev), torch.cumsum(d2, 0)])
+        mse = (cs[offs[1:]] - cs[offs[:-1]]) / npx
+        return (10.0 * torch.log10(255.0 ** 2 / mse)).cpu().numpy()
+
+    x0 = torch.log(f)
+    x, xp, L = x0.clone(), x0.clone(), [1.0] * n_images
+    traj = [psnrs(x)]
+    for _ in range(300):
+        L, _, _ = b.solve_from(f, x, xp, L, 1)
+        traj.append(psnrs(x))
+    traj = np.stack(traj)                          # [301, n]
+    target = traj[-1] - 0.01
+    ks = [_crossing(traj[:, i], target[i]) for i in range(n_images)]
+    ks = [300 if k is None else k for k in ks]
+    K = max(ks)
+
+    def prep():
+        prep.x, prep.xp = x0.clone(), x0.clone()
+
+    def run_batch(k):
+        return lambda: b.solve_from(f, prep.x, prep.xp, [1.0] * n_images, k)
+    t_batch = _wall_prepped(prep, run_batch(K))
+    t_batch300 = _wall_prepped(prep, run_batch(300), reps=2)
+    # one solver per image, run one after the other
+    singles = []
+    for i, (H, W) in enumerate(hw):
+        p = foe.default_params(H, W, looks=looks[i], max_iters=300)
+        singles.append(foe.Solver(p, bank, theta))
+    views = b.unpack(f)
+    x0v = [torch.log(v).contiguous() for v in views]
+    fv = [v.contiguous() for v in views]
+
+    def seq(kk):
+        def run():
+            for i, s in enumerate(singles):
+                if kk[i] > 0:
+                    xi, xpi = x0v[i].clone(), x0v[i].clone()
+                    s.solve_from(fv[i], xi, xpi, 1.0, kk[i])
+        return run
+    t_seq = _wall(seq(ks), reps=1)
+    t_seq300 = _wall(seq([300] * n_images), reps=1)
+    total_px = sum(H * W for H, W in hw)
+    for s in singles:
+        s.close()
+    b.close()
+    return {"workload": f"{n_images} images, sides U{{128..1024}} step 64, L in {{1,2,4,8}}, 300 iterations",
+            "tol_db": 0.01, "pixels": total_px, "iters_max": K, "iters_mean": round(float(np.mean(ks)), 1),
+            "seconds_batched": round(t_batch, 5), "seconds_one_by_one": round(t_seq, 5),
+            "speedup": round(t_seq / t_batch, 3),
+            "mpix_it_s_batched": round(total_px * 300 / t_batch300 / 1e6, 1),
+            "mpix_it_s_one_by_one": round(total_px * 300 / t_seq300 / 1e6, 1),
+            "latency_s_batched_all_images": round(t_batch300, 4),
+            "latency_s_one_by_one_mean_image": round(t_seq300 / n_images, 5)}
+
+
+def form_warm(dev):
+    """Learned warm start on a held-out 512 x 512 image against the plain solve from log f."""
+    import torch
+    import paper_1404_5344_amd as foe
+    import synth
+    from paper_1404_5344_amd import warmstart as ws
+    pr = synth.config5_eval(0)
+    bank, theta = synth.dct_bank(), synth.theta_weights(5)
+    f = torch.from_numpy(pr.f).to(dev)
+    clean = torch.from_numpy(pr.clean).to(dev)
+    s = foe.Solver(foe.default_params(512, 512, looks=pr.looks, max_iters=300), bank, theta)
+    net = ws.load()
+    x0 = torch.log(f)
+    u0 = net.infer(f.reshape(1, 512, 512)).reshape(512, 512)
+    plain = _probe(s, f, x0, clean, 255.0, 300)
+    warm = _probe(s, f, torch.log(u0), clean, 255.0, 40)
+    target = plain[-1] - 0.01
+    k_plain = _crossing(plain, target)
+    k_plain = 300 if k_plain is None else k_plain
+    k_warm = _crossing(warm, target)
+    prep, run = _run_from(s, f, x0, k_plain)
+    t_plain = _wall_prepped(prep, run)
+    f3 = f.reshape(1, 512, 512)
+    if k_warm is not None:
+        def run_w():
+            w = torch.log(net.infer(f3).reshape(512, 512))
+            if k_warm > 0:
+                s.solve_from(f, w, w.clone(), 1.0, k_warm)
+        fallback = False
+    else:   # the 40 warm iterations miss the target: the plain solve follows
+        def run_w():
+            w = torch.log(net.infer(f3).reshape(512, 512))
+            s.solve_from(f, w, w.clone(), 1.0, 40)
+            x, xp = x0.clone(), x0.clone()
+            s.solve_from(f, x, xp, 1.0, k_plain)
+        fallback = True
+    t_warm = _wall(run_w)
+    t_net = _wall(lambda: net.infer(f3))
+    net.close()
+    s.close()
+    return {"workload": "held-out 512x512 image, L=1; network + up to 40 iterations vs plain 300", "tol_db": 0.01,
+            "psnr_final_plain": round(plain[-1], 4), "psnr_network_only": round(warm[0], 4),
+            "psnr_network_plus_40": round(warm[-1], 4), "iters_plain": k_plain, "iters_warm": k_warm,
+            "fallback": fallback, "seconds_plain": round(t_plain, 5), "seconds_warm": round(t_warm, 5),
+            "seconds_network": round(t_net, 5), "speedup": round(t_plain / t_warm, 3)}
 
 
 def main():
@@ -57,10 +313,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device-to-device copy of this many MiB (a known-size kernel for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the workload is a single-GPU solve; multi-GPU runs are not "
-              "part of this build", file=sys.stderr)
+        print("bench.py measures one GPU: the workload is a single-GPU solve, and runs on several GPUs are "
+              "not provided", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -94,14 +354,24 @@ def main():
     psnr = synth.psnr(out.cpu().numpy(), pr.clean)
     log(f"bench: {dt * 1e3 / args.steps:.3f} ms/step, psnr {psnr:.4f} dB, trials/iter {trials_total / iters_total:.4f}")
 
-    # dominant kernel: fused trial kernel, mean of per-launch HIP event pairs on the solver stream
+    # dominant kernel: the fused trial kernel, mean of per-launch HIP event pairs on the solver stream
     ms_launch = s.profile_trial(50)
     flop = FLOP_PER_PX_TRIAL * H * W
     achieved = flop / (ms_launch * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "kernel": "fused_valu_kernel", "ms_per_launch": round(ms_launch, 5),
-                "flop_per_launch": flop}
+    traffic = measured_traffic()
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "kernel": "foe_trial_kernel (forward bank on FP32 MFMA, adjoint on VALU)",
+                "ms_per_launch": round(ms_launch, 5), "flop_per_launch": flop,
+                "kernel_source_hash": kernel_source_hash()}
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration, {n * 4} bytes read and written per copy")
     value = H * W * iters_total / dt / 1e6
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpixel-iters/s", "n_gpus": 1, "steps": args.steps,
@@ -114,10 +384,18 @@ def main():
                    "psnr_db": round(psnr, 4)},
         "roofline": roofline,
     }
+    s.close()
+    if not args.no_forms:
+        forms = {}
+        for name, fn in (("batched", form_batched), ("bf16", form_bf16), ("warm_start", form_warm)):
+            t = time.perf_counter()
+            log(f"bench: form {name}")
+            forms[name] = fn(dev)
+            log(f"bench: form {name}: {forms[name]} ({time.perf_counter() - t:.1f} s)")
+        res["forms"] = forms
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
         res["cpu_baseline"] = cpu_baseline(pr, bank, theta)
-    s.close()
     print(json.dumps(res), flush=True)
 
 

@@ -295,6 +295,18 @@ class BatchSolver(Solver):
         self.offsets = [int(o) for o in offs]
         self.shape = (self.offsets[-1],)
 
+    def solve_from(self, f_packed, x_cur, x_prev, L, iters: int, allow_failure=False):
+        """Advance every image's state (packed x_cur, x_prev; per-image L list) in place by `iters`
+        iterations; returns (L list, summaries, status)."""
+        self._sync_in()
+        n = self.n_images
+        Lc = (ctypes.c_double * n)(*[float(v) for v in L])
+        sums = (Summary * n)()
+        st = lib.foe_solve_from(self._h, _dev_ptr(f_packed, self.shape, "f"), _dev_ptr(x_cur, self.shape, "x_cur"),
+                                _dev_ptr(x_prev, self.shape, "x_prev"), Lc, int(iters), sums, None)
+        _check(st, (OK, ELINESEARCH, ENONFINITE) if allow_failure else (OK,))
+        return [Lc[i] for i in range(n)], [sums[i].as_dict() for i in range(n)], st
+
     def pack(self, images):
         torch = _torch()
         return torch.cat([torch.as_tensor(im, dtype=torch.float32).reshape(-1) for im in images]).contiguous()

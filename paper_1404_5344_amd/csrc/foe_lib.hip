@@ -24,7 +24,7 @@
 
 #include "../../include/foe.h"
 #include "common.hpp"
-#include "kernels_valu.hpp"
+#include "kernels_trial.hpp"
 #include "kernels_misc.hpp"
 
 using namespace foe;
@@ -149,11 +149,11 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
 template <int TW, int TH>
 void launch_cfg(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
   if (s->pb.engine == FWD_MFMA_BF16)
-    fused_valu_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16><<<s->nblocks, V_NT, 0, stream>>>(a);
+    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16><<<s->nblocks, V_NT, 0, stream>>>(a);
   else if (s->pb.engine == FWD_MFMA_F32)
-    fused_valu_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_F32><<<s->nblocks, V_NT, 0, stream>>>(a);
+    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_F32><<<s->nblocks, V_NT, 0, stream>>>(a);
   else
-    fused_valu_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU><<<s->nblocks, V_NT, 0, stream>>>(a);
+    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU><<<s->nblocks, V_NT, 0, stream>>>(a);
 }
 
 void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {

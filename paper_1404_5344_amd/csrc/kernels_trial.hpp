@@ -113,7 +113,7 @@ __device__ __forceinline__ bool slot_target(int s, int x0, int y0, int H, int W,
 // 4 right), so that the extended samples of the SYMMETRIC fold read 7x7 windows without
 // bounds checks; samples off the image are zero.
 template <int TW, int TH, int NC, int NT, int BR, int BC, int FWD>
-__global__ __launch_bounds__(NT) void fused_valu_kernel(FusedArgs a) {
+__global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   constexpr int W6 = TW + 4 * R, H6 = TH + 4 * R;
   constexpr int W3 = TW + 2 * R, H3 = TH + 2 * R;
   constexpr int PLANE3 = H3 * W3;

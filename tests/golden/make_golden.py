@@ -51,6 +51,38 @@ def config2(iters: int = 300):
     print("config2: psnr", out["psnr_noisy"], "->", out["psnr_final"], "in", dt, "s")
 
 
+def config4(iters: int = 300, index: int = 0):
+    pr = synth.config4(index)
+    bank = synth.dct_bank()
+    theta = synth.theta_weights(4)
+    p = oracle.Params(model=oracle.COMBINED, boundary=oracle.SYMMETRIC, lam1=pr.lam1, lam2=pr.lam2, beta=0.8)
+    t = time.time()
+    r = oracle.ipiano(p, pr.f, bank, theta, iters, L0=1.0)
+    dt = time.time() - t
+    u = r.u()
+    H, W = pr.f.shape
+    sample = list(range(0, H * W, 4099))
+    targets = np.argsort(pr.clean.ravel())[-40:].tolist()     # the 40 point targets
+    idx = sorted(set(sample) | set(targets))
+    out = {
+        "what": f"FP64 oracle, config 4 tile {index}: {H}x{W} SAR-like GRF image with 40 point targets, L = 1 "
+                "speckle, COMBINED model, SYMMETRIC boundary, DCT bank, theta seed 4, backtracking (L0 = 1, "
+                "eta_up = 2, eta_down = 1), beta = 0.8, 300 iterations; PSNR peak = max of the clean image",
+        "status": r.status,
+        "lam1": pr.lam1, "lam2": pr.lam2, "peak": pr.peak,
+        "psnr_noisy": synth.psnr(pr.f, pr.clean, pr.peak),
+        "psnr_final": synth.psnr(u, pr.clean, pr.peak),
+        "F": r.stats[:, 0].tolist(), "G": r.stats[:, 1].tolist(), "L": r.stats[:, 2].tolist(),
+        "trials": r.stats[:, 4].tolist(),
+        "u_sample_idx": idx,
+        "u_sample": u.ravel()[idx].tolist(),
+        "oracle_seconds": dt, "oracle_threads": oracle.get_threads(),
+    }
+    with open(os.path.join(HERE, f"config4_tile{index}_oracle.json"), "w") as fh:
+        json.dump(out, fh)
+    print("config4: psnr", out["psnr_noisy"], "->", out["psnr_final"], "in", dt, "s")
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["config2"]
     for w in which:
