@@ -110,8 +110,11 @@ __device__ __forceinline__ bool slot_target(int s, int x0, int y0, int H, int W,
 //
 // LDS layout: u6 holds u+ on the tile + 6 halo.  Each z plane holds z_j = theta_j rho'(y_j) on
 // the tile + 3 halo (R3), surrounded by a zero frame (3 rows above/below, 4 columns left and
-// 4 right), so that the extended samples of the SYMMETRIC fold read 7x7 windows without
-// bounds checks; samples off the image are zero.
+// 4 right), so that the 7x7 windows around the extended samples of the SYMMETRIC fold can be read
+// without bounds checks; samples off the image are zero.  The rows 0..4 and columns 0..5 of every
+// window lie inside the plane.  Only when the next tile holds 1 or 2 rows (columns) does the window
+// of a sample mirrored from the far image edge reach up to 2 rows (1 column) past the plane; those
+// samples are off the image, so the fold gives them zero weight and reads an in-plane address.
 template <int TW, int TH, int NC, int NT, int BR, int BC, int FWD>
 __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   constexpr int W6 = TW + 4 * R, H6 = TH + 4 * R;
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   __shared__ int act_off[NS];    // compacted fold slots: z-plane offset of the 7x7 window,
   __shared__ short act_slot[NS]; //                       the slot id
   __shared__ char act_rows[NS];  //                       and the window rows / columns that lie
-  __shared__ char act_cols[NS];  //                       inside the z plane (the rest is off the image)
+  __shared__ char act_cols[NS];  //                       inside the z plane (at least 5 / 6)
   __shared__ int wave_cnt[NT / 64];
   // taps of the current chunk, read by broadcast LDS loads so that the FMAs take them from VGPRs
   // (a VALU FMA with an SGPR operand issues at half rate on gfx950)
@@ -226,10 +229,6 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     for (int h = 0; h < 2; ++h) {
       int s = tid + h * NT, ply, plx, qy, qx;
       act[h] = s < NS && slot_target<TW, TH>(s, x0, y0, H, W, ply, plx, qy, qx);
-      // window top-left (tile coords qy - y0, qx - x0) in z-plane coordinates.  When the tile
-      // after this one holds fewer than 3 rows (columns), a mirrored sample lies up to 4 rows
-      // (columns) past the tile and its window reaches past the plane; those samples are off the
-      // image (zero), so the window is cut at the plane edge.
       const int wr = qy - y0 + ZR, wc = qx - x0 + ZC;
       off[h] = act[h] ? wr * W3P + wc : 0;
       nrow[h] = min(KS, H3P - wr);
@@ -288,8 +287,17 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
 #pragma unroll
     for (int j = 0; j < BC; ++j) acc[i][j] = 0.0f;
   float sacc[SLOTS_PT];
+  int s_off[SLOTS_PT], s_nr[SLOTS_PT], s_nc[SLOTS_PT];
+  bool s_live[SLOTS_PT];
 #pragma unroll
-  for (int k = 0; k < SLOTS_PT; ++k) sacc[k] = 0.0f;
+  for (int k = 0; k < SLOTS_PT; ++k) {
+    const int m = min(lt + k * GT, NS - 1);
+    sacc[k] = 0.0f;
+    s_live[k] = lt + k * GT < n_act;
+    s_off[k] = s_live[k] ? act_off[m] : 0;
+    s_nr[k] = s_live[k] ? act_rows[m] : KS;
+    s_nc[k] = s_live[k] ? act_cols[m] : KS;
+  }
 
   __syncthreads();
 
@@ -467,8 +475,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     __syncthreads();
 
     // ---- stage 3: adjoint bank.  Per filter of the group: the BR x BC block of this thread from a
-    // (BR+6) x (BC+6) window in registers, then the fold slots assigned to this thread (7x7 windows
-    // around extended samples; the taps are the same 49 scalars).
+    // (BR+6) x (BC+6) window in registers; then, on fold tiles, the fold slots assigned to this
+    // thread (7x7 windows around extended samples, the same 49 taps).
 #pragma unroll 1
     for (int jj = 0; jj < FPG; ++jj) {
       const int j = grp * FPG + jj;
@@ -501,20 +509,38 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
             for (int jx = 0; jx < BC; ++jx) acc[i][jx] = fmaf(kt[ta * KS + tb], wrow[jx + tb], acc[i][jx]);
         }
       }
-      if (fold) {
+    }
+    // the fold slots of this thread, filter by filter, in a pass of their own so that the window
+    // loads of the regular blocks and of the slots do not compete for registers
+    if (fold) {
+#pragma unroll 1
+      for (int jj = 0; jj < FPG; ++jj) {
+        const int j = grp * FPG + jj;
+        if (j >= ncur) break;
+        float kt[KAP];
+#pragma unroll
+        for (int t = 0; t < KAP; t += 4) {
+          float4 q4 = *reinterpret_cast<const float4*>(ka_s + j * KAP + t);
+          kt[t] = q4.x; kt[t + 1] = q4.y; kt[t + 2] = q4.z; kt[t + 3] = q4.w;
+        }
+        const float* zplane = zp + j * PLANEP;
 #pragma unroll
         for (int k = 0; k < SLOTS_PT; ++k) {
-          const int m = lt + k * GT;
-          if (m >= n_act) break;
-          const float* zw = zplane + act_off[m];
-          const int nr = act_rows[m], nc = act_cols[m];
+          if (!s_live[k]) break;
+          const float* zw = zplane + s_off[k];
           float v = 0.0f;
+          // branch-free: every load is issued unconditionally (window rows 5, 6 and column 6 past
+          // the plane are redirected in-plane and weighted zero)
 #pragma unroll
           for (int ta = 0; ta < KS; ++ta) {
-            if (ta >= nr) break;
+            const bool rok = ta < 5 || ta < s_nr[k];
+            const float* zr = zw + (rok ? ta : 0) * W3P;
 #pragma unroll
-            for (int tb = 0; tb < KS; ++tb)
-              if (tb < nc) v = fmaf(kt[ta * KS + tb], zw[ta * W3P + tb], v);
+            for (int tb = 0; tb < KS; ++tb) {
+              const bool ok = rok && (tb < 6 || tb < s_nc[k]);
+              const float w = ok ? kt[ta * KS + tb] : 0.0f;
+              v = fmaf(w, zr[ok ? tb : 0], v);
+            }
           }
           sacc[k] += v;
         }
