@@ -306,6 +306,39 @@ def form_warm(dev):
             "seconds_network": round(t_net, 5), "speedup": round(t_plain / t_warm, 3)}
 
 
+def form_unfused(dev, steps=5):
+    """The same 512 x 512 solve with the gradient split in two launches that exchange the 48 z planes
+    through HBM (forward half writes them, adjoint half reads them), against the fused kernel."""
+    import torch
+    import paper_1404_5344_amd as foe
+    import synth
+    pr = synth.config2()
+    bank, theta = synth.dct_bank(), synth.theta_weights(2)
+    H, W = pr.f.shape
+    f = torch.from_numpy(pr.f).to(dev)
+    out = {"workload": "512x512 config of the main line, 300 iterations, gradient unfused"}
+    for name, fusion in (("fused", 0), ("unfused", 1)):
+        p = foe.default_params(H, W, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=300, fusion=fusion)
+        s = foe.Solver(p, bank, theta)
+        s.solve(f)
+        t = _wall(lambda: s.solve(f), reps=steps)
+        r = s.solve(f)
+        out[f"mpix_it_s_{name}"] = round(H * W * r.summary["iters_done"] / t / 1e6, 1)
+        out[f"psnr_{name}"] = round(synth.psnr(r.u.cpu().numpy(), pr.clean), 4)
+        ms = s.profile_trial(50)
+        out[f"us_per_trial_{name}"] = round(ms * 1e3, 2)
+        if fusion:
+            # algorithmic HBM bytes of one unfused trial: forward half reads f, x^n, x^(n-1), grad F(x^n)
+            # (16 B/px) and writes x+ (4) and z (4 * 48); adjoint half reads z (4 * 48) and x+ (4) and
+            # writes grad F(x+) (4)
+            bpp = 16 + 4 + 4 * NF + 4 * NF + 4 + 4
+            out["algorithmic_bytes_per_px_trial"] = bpp
+            out["hbm_gb_s"] = round(bpp * H * W / (ms * 1e-3) / 1e9, 1)
+            out["hbm_frac_of_8tb_s"] = round(bpp * H * W / (ms * 1e-3) / 8e12, 4)
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +347,8 @@ def main():
     ap.add_argument("--iters", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--unfused", action="store_true",
+                    help="time the unfused gradient (z planes through HBM) on the main workload (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device-to-device copy of this many MiB (a known-size kernel for "
                          "scaling hardware byte counters)")
@@ -333,7 +368,8 @@ def main():
     pr = synth.config2()
     bank, theta = synth.dct_bank(), synth.theta_weights(2)
     H, W = pr.f.shape
-    p = foe.default_params(H, W, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=args.iters, looks=1)
+    p = foe.default_params(H, W, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=args.iters, looks=1,
+                           fusion=1 if args.unfused else 0)
     stream = torch.cuda.current_stream()
     s = foe.Solver(p, bank, theta, stream=stream)
     f = torch.from_numpy(pr.f).to(dev)
@@ -379,7 +415,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "512x512 shapes+cosine image, L=1 speckle, COMBINED model (lambda 160, 0.004), "
                                "48 DCT 7x7 filters, SYMMETRIC boundary, beta 0.8, backtracking, "
-                               f"{args.iters} iterations per step",
+                               f"{args.iters} iterations per step" + (", gradient unfused" if args.unfused else ""),
                    "pixels": H * W, "iterations": args.iters, "trials_per_iter": round(trials_total / iters_total, 4),
                    "psnr_db": round(psnr, 4)},
         "roofline": roofline,
@@ -387,7 +423,8 @@ def main():
     s.close()
     if not args.no_forms:
         forms = {}
-        for name, fn in (("batched", form_batched), ("bf16", form_bf16), ("warm_start", form_warm)):
+        for name, fn in (("batched", form_batched), ("bf16", form_bf16), ("warm_start", form_warm),
+                         ("unfused", form_unfused)):
             t = time.perf_counter()
             log(f"bench: form {name}")
             forms[name] = fn(dev)

@@ -62,6 +62,7 @@ typedef enum foe_boundary { FOE_BC_SYMMETRIC = 0, FOE_BC_ZERO = 1, FOE_BC_PERIOD
 typedef enum foe_step_mode { FOE_STEP_BACKTRACK = 0, FOE_STEP_FIXED = 1 } foe_step_mode;
 typedef enum foe_precision { FOE_PREC_FP32 = 0, FOE_PREC_BF16 = 1 } foe_precision;
 typedef enum foe_engine { FOE_ENGINE_AUTO = 0, FOE_ENGINE_VALU = 1, FOE_ENGINE_MFMA = 2 } foe_engine;
+typedef enum foe_fusion { FOE_FUSED = 0, FOE_UNFUSED = 1 } foe_fusion;
 
 /* Solver parameters.  foe_default_params() fills every field. */
 typedef struct foe_params {
@@ -78,7 +79,9 @@ typedef struct foe_params {
   int32_t newton_iters;    /* log-model prox: at most this many Newton iterations per pixel (each
                               pixel stops when converged), 1 .. 100 */
   int32_t engine;          /* foe_engine: VALU direct convolution or MFMA implicit GEMM */
-  int32_t reserved;
+  int32_t fusion;          /* foe_fusion: FUSED keeps the 48 z planes on chip; UNFUSED writes them to
+                              HBM between a forward and an adjoint launch (num_filters * pixels
+                              extra floats of device memory; same results up to summation order) */
   double lambda1, lambda2; /* < 0 => the paper's value for `looks` (log models only) */
   double beta;             /* inertia b in [0, 1) */
   double alpha_fixed;      /* step a of FOE_STEP_FIXED, > 0 */

@@ -90,6 +90,7 @@ struct foe_solver {
   float* gr[2] = {nullptr, nullptr};
   float* fbuf = nullptr;
   float* scratch = nullptr;  // probe workspace (one packed plane)
+  float* zbuf = nullptr;     // unfused path: num_filters packed planes of z
   float* kf = nullptr;
   float* ka = nullptr;
   float* theta = nullptr;
@@ -142,18 +143,32 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
   a.kf = s->kf;
   a.ka = s->ka;
   a.theta = s->theta;
+  a.zbuf = s->zbuf;
+  a.zstride = (long long)s->n;
   a.mode = mode;
   return a;
 }
 
+template <int TW, int TH, int UNF>
+void launch_engine(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
+  if (s->pb.engine == FWD_MFMA_BF16)
+    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
+  else if (s->pb.engine == FWD_MFMA_F32)
+    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_F32, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
+  else
+    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
+}
+
+// One trial (or evaluation): the fused kernel, or its two halves exchanging z through HBM.
 template <int TW, int TH>
 void launch_cfg(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
-  if (s->pb.engine == FWD_MFMA_BF16)
-    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16><<<s->nblocks, V_NT, 0, stream>>>(a);
-  else if (s->pb.engine == FWD_MFMA_F32)
-    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_F32><<<s->nblocks, V_NT, 0, stream>>>(a);
-  else
-    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU><<<s->nblocks, V_NT, 0, stream>>>(a);
+  if (s->zbuf) {
+    launch_engine<TW, TH, FWD_HALF>(s, a, stream);
+    // the adjoint half runs no forward bank: one instantiation serves every engine
+    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT, 0, stream>>>(a);
+  } else {
+    launch_engine<TW, TH, FUSED>(s, a, stream);
+  }
 }
 
 void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
@@ -189,6 +204,7 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   if (p->boundary < 0 || p->boundary > 2) return fail(FOE_EINVAL, "bad boundary");
   if (p->precision != FOE_PREC_FP32 && p->precision != FOE_PREC_BF16) return fail(FOE_EINVAL, "bad precision");
   if (p->engine < FOE_ENGINE_AUTO || p->engine > FOE_ENGINE_MFMA) return fail(FOE_EINVAL, "bad engine");
+  if (p->fusion != FOE_FUSED && p->fusion != FOE_UNFUSED) return fail(FOE_EINVAL, "bad fusion");
   if (p->precision == FOE_PREC_BF16 && p->engine == FOE_ENGINE_VALU)
     return fail(FOE_EINVAL, "BF16 precision runs on the MFMA engine");
   if (p->step_mode != FOE_STEP_BACKTRACK && p->step_mode != FOE_STEP_FIXED) return fail(FOE_EINVAL, "bad step_mode");
@@ -250,7 +266,7 @@ void destroy_all(foe_solver* s) {
   if (s->graph_one) (void)hipGraphExecDestroy(s->graph_one);
   for (float* p : s->xr) if (p) (void)hipFree(p);
   for (float* p : s->gr) if (p) (void)hipFree(p);
-  void* bufs[] = {s->fbuf, s->scratch, s->kf, s->ka, s->theta, s->partials, s->stats, s->st, s->d_images, s->d_tiles};
+  void* bufs[] = {s->fbuf, s->scratch, s->zbuf, s->kf, s->ka, s->theta, s->partials, s->stats, s->st, s->d_images, s->d_tiles};
   for (void* b : bufs) if (b) (void)hipFree(b);
   if (s->st_host) (void)hipHostFree(s->st_host);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
@@ -430,6 +446,7 @@ foe_status create_common(const foe_params* p, int n_img, const int32_t* H, const
   for (auto& x : s->xr) ok = ok && alloc((void**)&x, plane);
   for (auto& g : s->gr) ok = ok && alloc((void**)&g, plane);
   ok = ok && alloc((void**)&s->fbuf, plane) && alloc((void**)&s->scratch, plane);
+  if (p->fusion == FOE_UNFUSED) ok = ok && alloc((void**)&s->zbuf, plane * p->num_filters);
   ok = ok && alloc((void**)&s->kf, sizeof(float) * MAX_NF * KK) && alloc((void**)&s->ka, sizeof(float) * MAX_NF * KK);
   ok = ok && alloc((void**)&s->theta, sizeof(float) * MAX_NF);
   ok = ok && alloc((void**)&s->partials, sizeof(double) * PART_COLS * (size_t)s->max_tiles);
@@ -517,6 +534,7 @@ void foe_default_params(foe_params* p) {
   p->max_backtracks = 40;
   p->newton_iters = 30;
   p->engine = FOE_ENGINE_AUTO;
+  p->fusion = FOE_FUSED;
   p->lambda1 = -1.0;
   p->lambda2 = -1.0;
   p->beta = 0.8;

@@ -20,6 +20,11 @@ namespace foe {
 
 enum FusedMode { MODE_TRIAL = 0, MODE_EVAL = 1 };
 enum ForwardEngine { FWD_VALU = 0, FWD_MFMA_F32 = 1, FWD_MFMA_BF16 = 2 };
+// Fusion of the gradient: the whole trial in one kernel (FUSED), or split in two launches that
+// exchange the 48 z planes through HBM: FWD_HALF runs stages 1-2 (step, prox, forward bank,
+// energies) and stores z_i on the tile, ADJ_HALF loads z_i on the tile + 3 halo and runs stage 3
+// and the chain rule.
+enum Fusion { FUSED = 0, FWD_HALF = 1, ADJ_HALF = 2 };
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -38,6 +43,8 @@ struct FusedArgs {
                                         //   kf[(c * KK + a * 7 + b) * NC + j] = k_{c*NC+j}[6-a][6-b]
   const float* ka;                      // adjoint taps: ka[i][a][b] = k_i[a][b]
   const float* theta;
+  float* zbuf;                          // unfused z planes: zbuf[i * zstride + off + y * W + x]
+  long long zstride;
   int mode;
 };
 
@@ -115,7 +122,7 @@ __device__ __forceinline__ bool slot_target(int s, int x0, int y0, int H, int W,
 // window lie inside the plane.  Only when the next tile holds 1 or 2 rows (columns) does the window
 // of a sample mirrored from the far image edge reach up to 2 rows (1 column) past the plane; those
 // samples are off the image, so the fold gives them zero weight and reads an in-plane address.
-template <int TW, int TH, int NC, int NT, int BR, int BC, int FWD>
+template <int TW, int TH, int NC, int NT, int BR, int BC, int FWD, int UNF = FUSED>
 __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   constexpr int W6 = TW + 4 * R, H6 = TH + 4 * R;
   constexpr int W3 = TW + 2 * R, H3 = TH + 2 * R;
@@ -181,11 +188,22 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     go = a.g_out + im.off;
   }
   const float* __restrict__ f = a.f + im.off;
-  const bool fold = bc == SYMMETRIC && (y0 < R || y0 + TH > H - R || x0 < R || x0 + TW > W - R);
+  const bool fold = UNF != FWD_HALF && bc == SYMMETRIC && (y0 < R || y0 + TH > H - R || x0 < R || x0 + TW > W - R);
 
   double accF = 0.0, accG = 0.0, accS1 = 0.0, accS2 = 0.0, accM = 0.0;
 
-  // ---- stage 1: step + prox on tile + 6 halo -> u6
+  // ---- stage 1: step + prox on tile + 6 halo -> u6 (ADJ_HALF: u+ = e^{x+} on the tile only, x+
+  // as written by FWD_HALF)
+  if constexpr (UNF == ADJ_HALF) {
+    const float* xs = a.mode == MODE_TRIAL ? xo : xc;
+    for (int idx = tid; idx < TH * TW; idx += NT) {
+      const int i = idx / TW, jx = idx - i * TW, py = y0 + i, px = x0 + jx;
+      if (py < H && px < W) {
+        const float xn = xs[(size_t)py * W + px];
+        u6[(i + 2 * R) * W6 + jx + 2 * R] = logm ? fast_exp(xn) : xn;
+      }
+    }
+  } else
   for (int idx = tid; idx < H6 * W6; idx += NT) {
     int r = idx / W6, c = idx - r * W6;
     int gy = y0 - 2 * R + r, gx = x0 - 2 * R + c;
@@ -310,7 +328,24 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       ka_s[t] = tt < KK ? a.ka[(size_t)(c0 + j) * KK + tt] : 0.0f;
     }
     __syncthreads();
-    if constexpr (FWD == FWD_MFMA_BF16) {
+    if constexpr (UNF == ADJ_HALF) {
+      // ---- z of this chunk from HBM on the tile + 3 halo (zero off the image, wrapped when periodic);
+      // the positions of this thread are the ones of the VALU forward (fbase / zofs / flive)
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        if (fbase[k] < 0) continue;
+        const int idx = tid + k * NT, r = idx / W3, c = idx - r * W3;
+        int gy = y0 - R + r, gx = x0 - R + c;
+        gy = gy < 0 ? gy + H : (gy >= H ? gy - H : gy);
+        gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
+        const float* src = a.zbuf + (size_t)c0 * a.zstride + im.off + (size_t)gy * W + gx;
+        float zv[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) zv[j] = flive[k] && j < ncur ? src[(size_t)j * a.zstride] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) zp[j * PLANEP + zofs[k]] = zv[j];
+      }
+    } else if constexpr (FWD == FWD_MFMA_BF16) {
       // ---- stage 2 (matrix cores, BF16 operands, FP32 accumulation): v_mfma_f32_16x16x32_bf16 with
       // lane (m = lane % 16, k = lane / 16) holding taps 32s + 8k .. 32s + 8k + 7 of filter m (A) and the
       // same taps of position m (B).  The B values are differences u(p + t) - u(p) to the position's own
@@ -375,6 +410,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           const float den = fmaf(yv, yv, 1.0f);
           const float z = thv[j] * 2.0f * yv * fast_rcp(den);
           if (inr) zp[(4 * lk + j) * PLANEP + zo] = live ? z : 0.0f;
+          if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
+            a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
           e = fmaf(thv[j], fast_log(den), e);
         }
         if (own) accF += (double)e;
@@ -419,6 +456,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           const float den = fmaf(yv, yv, 1.0f);
           const float z = thv[j] * 2.0f * yv * fast_rcp(den);
           if (inr) zp[(4 * lk + j) * PLANEP + zo] = live ? z : 0.0f;
+          if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
+            a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
           e = fmaf(thv[j], fast_log(den), e);
         }
         if (own) accF += (double)e;
@@ -467,6 +506,10 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           float den = fmaf(y[k][j], y[k][j], 1.0f);
           float z = th * 2.0f * y[k][j] * fast_rcp(den);
           zp[j * PLANEP + zofs[k]] = flive[k] ? z : 0.0f;
+          if (UNF == FWD_HALF && fown[k] && j < ncur) {
+            const int idx = tid + k * NT, r = idx / W3, c = idx - r * W3;
+            a.zbuf[(size_t)(c0 + j) * a.zstride + im.off + (size_t)(y0 - R + r) * W + (x0 - R + c)] = z;
+          }
           e = fmaf(th, fast_log(den), e);
         }
         if (fown[k]) accF += (double)e;
@@ -478,7 +521,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     // (BR+6) x (BC+6) window in registers; then, on fold tiles, the fold slots assigned to this
     // thread (7x7 windows around extended samples, the same 49 taps).
 #pragma unroll 1
-    for (int jj = 0; jj < FPG; ++jj) {
+    for (int jj = 0; jj < (UNF == FWD_HALF ? 0 : FPG); ++jj) {
       const int j = grp * FPG + jj;
       if (j >= ncur) break;
       float kt[KAP];
@@ -550,6 +593,11 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   }
 
   // ---- epilogue: combine groups and fold slots in a fixed order, chain rule, store
+  if constexpr (UNF == FWD_HALF) {
+    double v[5] = {accF, accG, accS1, accS2, accM};
+    block_partials<NT, 5>(v, red, a.partials);
+    return;
+  }
   float* gsum = zp;                       // [NG][TH][TW]
   float* slots = zp + NG * TH * TW;       // [NG][NS]
 #pragma unroll
@@ -592,8 +640,10 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     go[(size_t)py * W + px] = g;
   }
 
-  double v[5] = {accF, accG, accS1, accS2, accM};
-  block_partials<NT, 5>(v, red, a.partials);
+  if constexpr (UNF == FUSED) {
+    double v[5] = {accF, accG, accS1, accS2, accM};
+    block_partials<NT, 5>(v, red, a.partials);
+  }
 }
 
 }  // namespace foe
