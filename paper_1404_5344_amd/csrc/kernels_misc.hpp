@@ -46,25 +46,23 @@ enum DecideMode { DECIDE_STEP = 0, DECIDE_INIT = 1, DECIDE_REPORT = 2 };
 // on acceptance rotate the x and gradient rings and record the stats row; on rejection
 // L <- eta_up L.  FIXED mode always accepts.
 // One block per image: block b reduces the partials of image b's tiles.
-__global__ __launch_bounds__(256) void decide_kernel(DevState* states, const double* __restrict__ partials,
-                                                     const ImageDesc* images, Problem pb, double* stats_all,
-                                                     int stats_rows, int mode) {
-  DevState* st = states + blockIdx.x;
-  double* stats = stats_all + (size_t)blockIdx.x * stats_rows * STAT_COLS;
-  const ImageDesc im = images[blockIdx.x];
-  if (mode == DECIDE_STEP && st->done) return;
+// The decision for one image, run by the first 256 threads of a block (every thread of the block
+// calls it: it contains a barrier).  The sums take the same fixed order wherever it runs.
+__device__ __forceinline__ void decide_block(DevState* st, const double* __restrict__ partials, const ImageDesc& im,
+                                             const Problem& pb, double* stats, int mode) {
   __shared__ double red[256 / 64][5];
   double v[5] = {0, 0, 0, 0, 0};
-  for (int b = im.tile0 + threadIdx.x; b < im.tile0 + im.ntiles; b += 256)
+  if (threadIdx.x < 256)
+    for (int b = im.tile0 + threadIdx.x; b < im.tile0 + im.ntiles; b += 256)
 #pragma unroll
-    for (int k = 0; k < 5; ++k) v[k] += partials[(size_t)b * PART_COLS + k];
+      for (int k = 0; k < 5; ++k) v[k] += partials[(size_t)b * PART_COLS + k];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     double x = v[k];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) red[wave][k] = x;
+    if (lane == 0 && wave < 4) red[wave][k] = x;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -120,6 +118,16 @@ __global__ __launch_bounds__(256) void decide_kernel(DevState* states, const dou
     st->L = pb.eta_up * L;
     st->alpha = 1.9 * (1.0 - pb.beta_d) / st->L;
   }
+}
+
+// One block per image: block b reduces the partials of image b's tiles and decides.
+__global__ __launch_bounds__(256) void decide_kernel(DevState* states, const double* __restrict__ partials,
+                                                     const ImageDesc* images, Problem pb, double* stats_all,
+                                                     int stats_rows, int mode) {
+  DevState* st = states + blockIdx.x;
+  if (mode == DECIDE_STEP && st->done) return;
+  const ImageDesc im = images[blockIdx.x];
+  decide_block(st, partials, im, pb, stats_all + (size_t)blockIdx.x * stats_rows * STAT_COLS, mode);
 }
 
 // u = e^{x^n} (log models) or x^n, from the ring slot each image's state names.

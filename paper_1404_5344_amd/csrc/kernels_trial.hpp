@@ -434,33 +434,48 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       float thv[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) thv[j] = 4 * lk + j < ncur ? a.theta[c0 + 4 * lk + j] : 0.0f;
+      // two position groups per pass: two independent accumulator chains keep the matrix pipe busy
+      // while each MFMA waits for its predecessor
 #pragma unroll 1
-      for (int g = wave; g < NGROUP; g += NT / 64) {
-        const int p = g * 16 + lm;
-        const bool inr = p < PLANE3;
-        const int r = inr ? p / W3 : 0, c = inr ? p - (p / W3) * W3 : 0;
-        const int pbase = r * W6 + c;
-        floatx4 acc4 = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int g0 = wave; g0 < NGROUP; g0 += 2 * (NT / 64)) {
+        int pb2[2], rr[2], cc[2];
+        bool inr2[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int p = (g0 + h * (NT / 64)) * 16 + lm;
+          inr2[h] = p < PLANE3;
+          rr[h] = inr2[h] ? p / W3 : 0;
+          cc[h] = inr2[h] ? p - rr[h] * W3 : 0;
+          pb2[h] = rr[h] * W6 + cc[h];
+        }
+        floatx4 acc2[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
         for (int s = 0; s < 13; ++s)
-          acc4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a_reg[s], u6[pbase + toff[s]], acc4, 0, 0, 0);
-        const int gy = y0 - R + r, gx = x0 - R + c;
-        const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-        const bool live = inr && (inimg || bc == PERIODIC);
-        const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
-        const int zo = (r + ZR) * W3P + c + ZC;
-        float e = 0.0f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float yv = acc4[j];
-          const float den = fmaf(yv, yv, 1.0f);
-          const float z = thv[j] * 2.0f * yv * fast_rcp(den);
-          if (inr) zp[(4 * lk + j) * PLANEP + zo] = live ? z : 0.0f;
-          if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
-            a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
-          e = fmaf(thv[j], fast_log(den), e);
+          for (int h = 0; h < 2; ++h)
+            acc2[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_reg[s], u6[pb2[h] + toff[s]], acc2[h], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = rr[h], c = cc[h];
+          const bool inr = inr2[h];
+          const int gy = y0 - R + r, gx = x0 - R + c;
+          const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+          const bool live = inr && (inimg || bc == PERIODIC);
+          const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
+          const int zo = (r + ZR) * W3P + c + ZC;
+          float e = 0.0f;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float yv = acc2[h][j];
+            const float den = fmaf(yv, yv, 1.0f);
+            const float z = thv[j] * 2.0f * yv * fast_rcp(den);
+            if (inr) zp[(4 * lk + j) * PLANEP + zo] = live ? z : 0.0f;
+            if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
+              a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
+            e = fmaf(thv[j], fast_log(den), e);
+          }
+          if (own) accF += (double)e;
         }
-        if (own) accF += (double)e;
       }
     } else {
       // ---- stage 2: forward bank on tile + 3 halo; one row of taps of 8 filters (in SGPRs) per pass
@@ -571,18 +586,21 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         for (int k = 0; k < SLOTS_PT; ++k) {
           if (!s_live[k]) break;
           const float* zw = zplane + s_off[k];
+          // branch-free: every load is issued unconditionally.  Window rows 5, 6 and column 6 that
+          // would leave the plane read the last in-plane row / column instead and are weighted zero
+          // (row and column offsets and weights are arithmetic, so no load waits behind a branch).
+          const int rofs5 = min(5, s_nr[k] - 1) * W3P, rofs6 = min(6, s_nr[k] - 1) * W3P;
+          const int cofs6 = min(6, s_nc[k] - 1);
+          const float m5 = (float)(s_nr[k] > 5), m6 = (float)(s_nr[k] > 6), mc6 = (float)(s_nc[k] > 6);
           float v = 0.0f;
-          // branch-free: every load is issued unconditionally (window rows 5, 6 and column 6 past
-          // the plane are redirected in-plane and weighted zero)
 #pragma unroll
           for (int ta = 0; ta < KS; ++ta) {
-            const bool rok = ta < 5 || ta < s_nr[k];
-            const float* zr = zw + (rok ? ta : 0) * W3P;
+            const float* zr = zw + (ta < 5 ? ta * W3P : (ta == 5 ? rofs5 : rofs6));
+            const float mr = ta < 5 ? 1.0f : (ta == 5 ? m5 : m6);
 #pragma unroll
             for (int tb = 0; tb < KS; ++tb) {
-              const bool ok = rok && (tb < 6 || tb < s_nc[k]);
-              const float w = ok ? kt[ta * KS + tb] : 0.0f;
-              v = fmaf(w, zr[ok ? tb : 0], v);
+              const float w = tb < 6 ? kt[ta * KS + tb] : kt[ta * KS + tb] * mc6;
+              v = fmaf(ta < 5 ? w : w * mr, zr[tb < 6 ? tb : cofs6], v);
             }
           }
           sacc[k] += v;
