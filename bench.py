@@ -339,6 +339,30 @@ def form_unfused(dev, steps=5):
     return out
 
 
+def form_lambertw(dev, steps=5):
+    """LOG model (lambda2 = 0) on the 512 x 512 image: the prox of eq. (subproblem) by Newton's method
+    and by its Lambert-W closed form."""
+    import paper_1404_5344_amd as foe
+    import synth
+    import torch
+    pr = synth.config2()
+    bank, theta = synth.dct_bank(), synth.theta_weights(2)
+    H, W = pr.f.shape
+    f = torch.from_numpy(pr.f).to(dev)
+    out = {"workload": "512x512 image of the main line, LOG model (lambda 160, 0), 300 iterations"}
+    for name, method in (("newton", 0), ("lambertw", 1)):
+        p = foe.default_params(H, W, model=1, lambda1=pr.lam1, lambda2=0.0, max_iters=300, prox_method=method)
+        s = foe.Solver(p, bank, theta)
+        s.solve(f)
+        t = _wall(lambda: s.solve(f), reps=steps)
+        r = s.solve(f)
+        out[f"mpix_it_s_{name}"] = round(H * W * r.summary["iters_done"] / t / 1e6, 1)
+        out[f"psnr_{name}"] = round(synth.psnr(r.u.cpu().numpy(), pr.clean), 4)
+        out[f"us_per_trial_{name}"] = round(s.profile_trial(50) * 1e3, 2)
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -424,7 +448,7 @@ def main():
     if not args.no_forms:
         forms = {}
         for name, fn in (("batched", form_batched), ("bf16", form_bf16), ("warm_start", form_warm),
-                         ("unfused", form_unfused)):
+                         ("unfused", form_unfused), ("lambertw", form_lambertw)):
             t = time.perf_counter()
             log(f"bench: form {name}")
             forms[name] = fn(dev)

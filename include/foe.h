@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define FOE_ABI_VERSION 1
+#define FOE_ABI_VERSION 2
 #define FOE_MAX_FILTERS 64
 #define FOE_KSIZE 7
 #define FOE_STATS_COLS 8
@@ -63,6 +63,7 @@ typedef enum foe_step_mode { FOE_STEP_BACKTRACK = 0, FOE_STEP_FIXED = 1 } foe_st
 typedef enum foe_precision { FOE_PREC_FP32 = 0, FOE_PREC_BF16 = 1 } foe_precision;
 typedef enum foe_engine { FOE_ENGINE_AUTO = 0, FOE_ENGINE_VALU = 1, FOE_ENGINE_MFMA = 2 } foe_engine;
 typedef enum foe_fusion { FOE_FUSED = 0, FOE_UNFUSED = 1 } foe_fusion;
+typedef enum foe_prox { FOE_PROX_NEWTON = 0, FOE_PROX_LAMBERTW = 1 } foe_prox;
 
 /* Solver parameters.  foe_default_params() fills every field. */
 typedef struct foe_params {
@@ -82,6 +83,9 @@ typedef struct foe_params {
   int32_t fusion;          /* foe_fusion: FUSED keeps the 48 z planes on chip; UNFUSED writes them to
                               HBM between a forward and an adjoint launch (num_filters * pixels
                               extra floats of device memory; same results up to summation order) */
+  int32_t prox_method;     /* foe_prox: NEWTON solves eq. (subproblem) by safeguarded Newton (every log
+                              model); LAMBERTW evaluates its closed form through the principal branch of
+                              Lambert's W, the direct solver Sec. II-C mentions (LOG model only, else EINVAL) */
   double lambda1, lambda2; /* < 0 => the paper's value for `looks` (log models only) */
   double beta;             /* inertia b in [0, 1) */
   double alpha_fixed;      /* step a of FOE_STEP_FIXED, > 0 */

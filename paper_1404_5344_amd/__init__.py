@@ -34,7 +34,7 @@ class FoeError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "height", "width", "num_filters", "ksize", "model", "boundary", "precision", "step_mode", "looks",
-        "max_iters", "max_backtracks", "newton_iters", "engine", "fusion")] + \
+        "max_iters", "max_backtracks", "newton_iters", "engine", "fusion", "prox_method")] + \
         [(n, ctypes.c_double) for n in ("lambda1", "lambda2", "beta", "alpha_fixed", "L0", "eta_up", "eta_down")]
 
 

@@ -57,6 +57,7 @@ struct Problem {
   int nf;
   int model, bc, step_mode;
   int max_backtracks, newton_iters;
+  int prox_method;  // 0 Newton, 1 Lambert W (LOG model)
   int engine;  // forward-bank engine of the fused kernel
   float beta;
   double beta_d, eta_up, eta_down, alpha_fixed;

@@ -51,8 +51,38 @@ __device__ __forceinline__ float data_term(float x, float u, float f, int model,
 // pixel's result depends only on its own inputs.
 // IDIV: the positive root of (1 + tau lam) u^2 - xh u - tau lam f^2 = 0, in the form
 // without cancellation for xh < 0.
+// LOG model, direct solve (Sec. II-C names the Lambert W route).  In t = w - log f the prox minimises
+// (t - t_hat)^2 / 2 + a (t + e^{-2t} / 2), a = tau lam1, whose optimality condition
+// t - t_hat + a (1 - e^{-2t}) = 0 has the solution t = t_hat - a + y / 2, y = W0(z), z = 2 a e^{2 (a - t_hat)}
+// (W0 = principal branch of Lambert's W).  Since y + ln y = ln z, this equals t = (ln 2a - ln y) / 2, which
+// has no cancellation when a and y / 2 are both large.  y is taken from ln z (no overflow for large z) by
+// three Newton steps on y + ln y = ln z, started from ln z - ln ln z (ln z > 1) or z / (1 + z); for
+// ln z < -60, ln y = ln z to FP32 accuracy.
+__device__ __forceinline__ float prox_log_lambertw(float xh, float f, float tau, float lam1) {
+  const float a = tau * lam1;
+  if (!(a > 0.0f)) return xh;
+  const float lf = fast_log(f);
+  const float l2a = fast_log(2.0f * a);
+  const float lnz = l2a + 2.0f * (a - (xh - lf));
+  float lny = lnz;
+  if (lnz > -60.0f) {
+    float y;
+    if (lnz > 1.0f) {
+      y = lnz - fast_log(lnz);
+    } else {
+      const float z = fast_exp(lnz);
+      y = z * fast_rcp(1.0f + z);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) y = y * (1.0f + lnz - fast_log(y)) * fast_rcp(1.0f + y);
+    lny = fast_log(y);
+  }
+  return 0.5f * (l2a - lny) + lf;
+}
+
 __device__ __forceinline__ float prox_pixel(float xh, float f, float tau, int model, float lam1, float lam2,
-                                            int max_iters) {
+                                            int max_iters, int method = 0) {
+  if (method == 1) return prox_log_lambertw(xh, f, tau, lam1);
   if (model == IDIV) {
     float a = 1.0f + tau * lam1;
     float c = tau * lam1 * f * f;

@@ -205,6 +205,9 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   if (p->precision != FOE_PREC_FP32 && p->precision != FOE_PREC_BF16) return fail(FOE_EINVAL, "bad precision");
   if (p->engine < FOE_ENGINE_AUTO || p->engine > FOE_ENGINE_MFMA) return fail(FOE_EINVAL, "bad engine");
   if (p->fusion != FOE_FUSED && p->fusion != FOE_UNFUSED) return fail(FOE_EINVAL, "bad fusion");
+  if (p->prox_method != FOE_PROX_NEWTON && p->prox_method != FOE_PROX_LAMBERTW) return fail(FOE_EINVAL, "bad prox_method");
+  if (p->prox_method == FOE_PROX_LAMBERTW && p->model != FOE_MODEL_LOG)
+    return fail(FOE_EINVAL, "the Lambert-W prox exists for the LOG model only");
   if (p->precision == FOE_PREC_BF16 && p->engine == FOE_ENGINE_VALU)
     return fail(FOE_EINVAL, "BF16 precision runs on the MFMA engine");
   if (p->step_mode != FOE_STEP_BACKTRACK && p->step_mode != FOE_STEP_FIXED) return fail(FOE_EINVAL, "bad step_mode");
@@ -228,6 +231,7 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   pb->step_mode = p->step_mode;
   pb->max_backtracks = p->max_backtracks;
   pb->newton_iters = p->newton_iters;
+  pb->prox_method = p->prox_method;
   pb->beta = (float)p->beta;
   pb->beta_d = p->beta;
   pb->eta_up = p->eta_up;
@@ -535,6 +539,7 @@ void foe_default_params(foe_params* p) {
   p->newton_iters = 30;
   p->engine = FOE_ENGINE_AUTO;
   p->fusion = FOE_FUSED;
+  p->prox_method = FOE_PROX_NEWTON;
   p->lambda1 = -1.0;
   p->lambda2 = -1.0;
   p->beta = 0.8;

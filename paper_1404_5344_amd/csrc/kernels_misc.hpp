@@ -158,7 +158,7 @@ __global__ void export_state_kernel(const DevState* states, const float* x0, con
 __global__ void prox_probe_kernel(const float* __restrict__ xh, const float* __restrict__ f, float* out, size_t n,
                                   float tau, Problem pb, float lam1, float lam2) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    out[i] = prox_pixel(xh[i], f[i], tau, pb.model, lam1, lam2, pb.newton_iters);
+    out[i] = prox_pixel(xh[i], f[i], tau, pb.model, lam1, lam2, pb.newton_iters, pb.prox_method);
 }
 
 }  // namespace foe

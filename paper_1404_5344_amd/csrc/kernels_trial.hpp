@@ -217,7 +217,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       if (a.mode == MODE_TRIAL) {
         float xv = xc[p], xpv = xp[p], gv = gc[p];
         float xh = xv - alpha * gv + pb.beta * (xv - xpv);
-        xn = prox_pixel(xh, fv, alpha, model, lam1, lam2, pb.newton_iters);
+        xn = prox_pixel(xh, fv, alpha, model, lam1, lam2, pb.newton_iters, pb.prox_method);
         uval = logm ? fast_exp(xn) : xn;
         if (own) {
           xo[p] = xn;

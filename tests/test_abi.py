@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_host_only_calls():
     import paper_1404_5344_amd as foe
-    assert foe.lib.foe_abi_version() == 1
+    assert foe.lib.foe_abi_version() == 2
     assert foe.status_str(foe.ELINESEARCH) == "FOE_ELINESEARCH"
     p = foe.default_params(64, 64)
     assert p.num_filters == 48 and p.ksize == 7 and p.max_iters == 300 and p.beta == 0.8 and p.newton_iters == 30
