@@ -412,6 +412,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     psnr = synth.psnr(out.cpu().numpy(), pr.clean)
+    ssim = foe.ssim(out, torch.from_numpy(pr.clean.astype(np.float32)).to(dev))
     log(f"bench: {dt * 1e3 / args.steps:.3f} ms/step, psnr {psnr:.4f} dB, trials/iter {trials_total / iters_total:.4f}")
 
     # dominant kernel: the fused trial kernel, mean of per-launch HIP event pairs on the solver stream
@@ -441,7 +442,7 @@ def main():
                                "48 DCT 7x7 filters, SYMMETRIC boundary, beta 0.8, backtracking, "
                                f"{args.iters} iterations per step" + (", gradient unfused" if args.unfused else ""),
                    "pixels": H * W, "iterations": args.iters, "trials_per_iter": round(trials_total / iters_total, 4),
-                   "psnr_db": round(psnr, 4)},
+                   "psnr_db": round(psnr, 4), "ssim": round(ssim, 5)},
         "roofline": roofline,
     }
     s.close()

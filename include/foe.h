@@ -219,6 +219,15 @@ foe_status foe_cnn_loss_grad(foe_cnn* c, const float* d_f, const float* d_target
 foe_status foe_cnn_train_step(foe_cnn* c, const float* d_f, const float* d_target_u, int32_t n, int32_t H, int32_t W,
                               double lr, double* loss);
 
+/* ---- Quality index (reporting; not part of the iteration).  *ssim_out = the mean SSIM of d_u
+ * against d_ref (both device planes H x W, row-major) with the 11 x 11 Gaussian window of standard
+ * deviation 1.5, C1 = (0.01 peak)^2, C2 = (0.03 peak)^2, over the (H - 10) x (W - 10) positions where
+ * the window lies inside the image -- the SSIM index the paper reports with PSNR (Sec. III-B).  Runs on
+ * hip_stream (NULL = null stream) and synchronises it; allocates and frees a small block-sum buffer.
+ * Errors: EINVAL (NULL, an image smaller than 11 x 11, peak <= 0), ENOMEM, EDEVICE. */
+foe_status foe_ssim(const float* d_u, const float* d_ref, int32_t H, int32_t W, double peak, void* hip_stream,
+                    double* ssim_out);
+
 const char* foe_status_str(foe_status st);
 const char* foe_last_error(void);
 int32_t foe_abi_version(void);

@@ -247,3 +247,6 @@ def cnn_relu_margin(params, f) -> float:
     L.ora_cnn_relu_margin.argtypes = [_D, _D, _I, _I, _I]
     L.ora_cnn_relu_margin.restype = ctypes.c_double
     return float(L.ora_cnn_relu_margin(_p(params), _p(f), n, H, W))
+
+
+from .quality import ssim, ssim_map  # noqa: E402,F401  (FP64 SSIM, quality reporting)

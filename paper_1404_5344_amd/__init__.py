@@ -85,6 +85,8 @@ def _load():
     L.foe_cnn_loss_grad.argtypes = [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _DP, _VP]
     L.foe_cnn_train_step.argtypes = [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                      _DP]
+    L.foe_ssim.argtypes = [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _VP, _DP]
+    L.foe_ssim.restype = ctypes.c_int
     L.foe_status_str.argtypes = [ctypes.c_int]
     L.foe_status_str.restype = ctypes.c_char_p
     L.foe_last_error.argtypes = []
@@ -412,3 +414,15 @@ class WarmStartNet:
         _check(lib.foe_cnn_train_step(self._h, _dev_ptr(f, None, "f"), _dev_ptr(u_target, f.shape, "u_target"), n,
                                       H, W, float(lr), ctypes.byref(loss)))
         return loss.value
+
+
+def ssim(u, ref, peak: float = 255.0, stream=None) -> float:
+    """Mean SSIM of u against ref (float32 CUDA tensors [H, W]) on the GPU (see foe_ssim)."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    H, W = u.shape
+    out = ctypes.c_double()
+    _check(lib.foe_ssim(_dev_ptr(u, None, "u"), _dev_ptr(ref, (H, W), "ref"), H, W, float(peak),
+                        _VP(stream.cuda_stream), ctypes.byref(out)))
+    return out.value

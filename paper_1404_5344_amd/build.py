@@ -11,7 +11,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libfoe.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["foe_lib.hip", "cnn.hip"]
+SOURCES = ["foe_lib.hip", "cnn.hip", "quality.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
