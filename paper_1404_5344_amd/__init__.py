@@ -14,6 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libfoe.so")
+ABI_VERSION = 2   # FOE_ABI_VERSION of include/foe.h that the structures below mirror
 
 OK, EINVAL, ENOMEM, EDEVICE, ELINESEARCH, ENONFINITE, EINPUT = 0, 1, 2, 3, 4, 5, 6
 COMBINED, LOG, IDIV = 0, 1, 2
@@ -97,6 +98,8 @@ def _load():
                  "foe_batch_layout", "foe_batch_solve", "foe_autotune", "foe_set_tile_config", "foe_cnn_create",
                  "foe_cnn_destroy", "foe_cnn_get_params", "foe_cnn_infer", "foe_cnn_loss_grad", "foe_cnn_train_step"):
         getattr(L, name).restype = ctypes.c_int
+    if L.foe_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {L.foe_abi_version()}, this binding expects {ABI_VERSION}")
     return L
 
 

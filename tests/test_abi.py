@@ -36,7 +36,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_host_only_calls():
     import paper_1404_5344_amd as foe
-    assert foe.lib.foe_abi_version() == 2
+    assert foe.lib.foe_abi_version() == 2 == foe.ABI_VERSION
+    with open(os.path.join(ROOT, "include", "foe.h")) as fh:
+        assert "#define FOE_ABI_VERSION 2" in fh.read()
     assert foe.status_str(foe.ELINESEARCH) == "FOE_ELINESEARCH"
     p = foe.default_params(64, 64)
     assert p.num_filters == 48 and p.ksize == 7 and p.max_iters == 300 and p.beta == 0.8 and p.newton_iters == 30
