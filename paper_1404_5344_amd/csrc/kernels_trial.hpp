@@ -67,92 +67,55 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* red, dou
   }
 }
 
-// Fold slots of the SYMMETRIC boundary map: the extended samples q != p with source p, for
-// pixels p within 3 of the image border.  Slot layout (TW/TH = tile width/height):
-//   [0, 3TW)            y-low   q = (-1-py, px),        py in [0,2]
-//   [3TW, 6TW)          y-high  q = (2H-1-py, px),      py in [H-3, H-1]
-//   [6TW, 6TW+3TH)      x-low   q = (py, -1-px),        px in [0,2]
-//   [6TW+3TH, 6TW+6TH)  x-high  q = (py, 2W-1-px),      px in [W-3, W-1]
-//   [6TW+6TH, +36)      corners (y-low|y-high) x (x-low|x-high), 3x3 each
-// slot_target() returns the owning pixel p (tile-local) and the extended sample q, or false
-// when the slot is empty for this tile.
-template <int TW, int TH>
-__device__ __forceinline__ bool slot_target(int s, int x0, int y0, int H, int W, int& ply, int& plx, int& qy,
-                                            int& qx) {
-  int py, px;
-  if (s < 6 * TW) {
-    int hiy = s >= 3 * TW;
-    int ss = hiy ? s - 3 * TW : s;
-    int d = ss / TW;
-    px = x0 + (ss - d * TW);
-    py = hiy ? H - 1 - d : d;
-    qy = hiy ? 2 * H - 1 - py : -1 - py;
-    qx = px;
-  } else if (s < 6 * TW + 6 * TH) {
-    int s2 = s - 6 * TW;
-    int hix = s2 >= 3 * TH;
-    int ss = hix ? s2 - 3 * TH : s2;
-    int d = ss / TH;
-    py = y0 + (ss - d * TH);
-    px = hix ? W - 1 - d : d;
-    qx = hix ? 2 * W - 1 - px : -1 - px;
-    qy = py;
-  } else {
-    int s3 = s - 6 * TW - 6 * TH;
-    int corner = s3 / 9, rem = s3 - corner * 9;
-    int dy = rem / 3, dx = rem - dy * 3;
-    int hiy = corner >> 1, hix = corner & 1;
-    py = hiy ? H - 1 - dy : dy;
-    px = hix ? W - 1 - dx : dx;
-    qy = hiy ? 2 * H - 1 - py : -1 - py;
-    qx = hix ? 2 * W - 1 - px : -1 - px;
-  }
-  ply = py - y0;
-  plx = px - x0;
-  return ply >= 0 && ply < TH && plx >= 0 && plx < TW && py >= 0 && py < H && px >= 0 && px < W;
-}
+// Mirror terms of the SYMMETRIC boundary map (half-sample reflection, so x(-1-i) = x(i)).  The
+// adjoint on the extended domain gives every extended sample q (within 3 of the image, off it) the
+// value v(q) = sum_{a,b} k[a][b] z(q_y - 3 + a, q_x - 3 + b), and the gradient at the pixel p that q
+// mirrors to receives v(q).  z vanishes off the image, so only the window lines inside the image
+// count: a sample d = 0, 1, 2 lines outside an edge sees the 3 - d z lines nearest that edge through
+// the tap lines 4 + d .. 6 (low edge) or 2 - d .. 0 (high edge).  With Z_r the z line at distance r
+// from the edge and K_m the tap line 4 + m (low) or 2 - m (high), both taken along the edge,
+//   v(d) = sum_{r=0}^{2-d} <K_{d+r}, Z_r>   (7 products per line pair).
+// One fold item is one position along an edge and one filter: it forms v(0), v(1), v(2).  Items of
+// the y edges run over the TW columns of the tile; items of the x edges run over the TH rows of the
+// tile and, for the corners, over the extended rows -1-i (target row i) and H+i (target row H-1-i)
+// whose target row lies in the tile: a corner sample then is an x-edge item whose window rows off
+// the image read zeros.
+// Layout slots (partials fpart[(slot * 3 + d) * NC + j] in the epilogue):
+//   [0, TW) y-low, [TW, 2TW) y-high, then per x edge TH + 6 slots: the tile rows, the 3 low-corner
+//   rows (i = 0..2), the 3 high-corner rows (i = 0..2).
 
 // Tile configuration: TW x TH output tile, NC filters per LDS chunk, NT threads, adjoint
 // register blocks of BR x BC outputs per thread (NT / ((TH/BR) (TW/BC)) filter groups).
 //
 // LDS layout: u6 holds u+ on the tile + 6 halo.  Each z plane holds z_j = theta_j rho'(y_j) on
-// the tile + 3 halo (R3), surrounded by a zero frame (3 rows above/below, 4 columns left and
-// 4 right), so that the 7x7 windows around the extended samples of the SYMMETRIC fold can be read
-// without bounds checks; samples off the image are zero.  The rows 0..4 and columns 0..5 of every
-// window lie inside the plane.  Only when the next tile holds 1 or 2 rows (columns) does the window
-// of a sample mirrored from the far image edge reach up to 2 rows (1 column) past the plane; those
-// samples are off the image, so the fold gives them zero weight and reads an in-plane address.
+// the tile + 3 halo (R3, row stride W3), zero off the image except under the PERIODIC map; every
+// position of the planes is written in every chunk.  fpart holds the fold partials of the
+// SYMMETRIC map on tiles within 3 of the image border, accumulated over the chunks.
 template <int TW, int TH, int NC, int NT, int BR, int BC, int FWD, int UNF = FUSED>
 __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   constexpr int W6 = TW + 4 * R, H6 = TH + 4 * R;
   constexpr int W3 = TW + 2 * R, H3 = TH + 2 * R;
   constexpr int PLANE3 = H3 * W3;
-  constexpr int ZR = R, ZC = R + 1;               // zero frame: rows above, columns left
-  constexpr int W3P = W3 + ZC + R + 1, H3P = H3 + 2 * ZR;  // W3P even for float2 reads
-  constexpr int PLANEP = H3P * W3P;
+  constexpr int PLANE = H3 * W3;                  // one z plane: the tile + 3 halo, row stride W3
   constexpr int PPT = (PLANE3 + NT - 1) / NT;     // forward positions per thread
   constexpr int GT = (TH / BR) * (TW / BC);       // threads per adjoint group
   constexpr int NG = NT / GT;                     // filter groups
   constexpr int FPG = NC / NG;                    // filters per group per chunk
   constexpr int WR = BR + KS - 1, WC = BC + KS - 1;
-  constexpr int NS = 6 * TW + 6 * TH + 36;        // fold slots
-  constexpr int SLOTS_PT = (NS + GT - 1) / GT;    // compacted fold slots per thread (per group)
+  constexpr int NPX = TH + 6;                     // layout slots per x edge
+  constexpr int NSLOT = 2 * TW + 2 * NPX;          // fold layout slots
   static_assert(NT % GT == 0 && NC % NG == 0 && GT % 64 == 0 && TH % BR == 0 && TW % BC == 0, "bad tiling");
-  static_assert(BC % 2 == 0 && W3P % 2 == 0 && PLANEP % 2 == 0 && ZC % 2 == 0, "adjoint reads float2 pairs");
+  static_assert(BC % 2 == 0 && W3 % 2 == 0 && PLANE % 2 == 0, "adjoint reads float2 pairs");
   static_assert(NC % 8 == 0, "forward passes take 8 filters");
-  static_assert(NG * (TH * TW + NS) <= NC * PLANEP, "epilogue does not fit in the z buffer");
-  static_assert(NS <= 2 * NT, "fold slot scan covers at most two slots per thread");
+  static_assert(NG * TH * TW <= NC * PLANE, "epilogue does not fit in the z buffer");
+  static_assert((NC & (NC - 1)) == 0 && TH >= R && TW >= R, "fold items: NC a power of two, tiles >= 3");
   static_assert(FWD == FWD_VALU || NC == 16, "the MFMA forwards take one 16-filter block per chunk");
   constexpr int NGROUP = (PLANE3 + 15) / 16;      // MFMA forward: groups of 16 consecutive positions
 
   __shared__ float u6[H6 * W6];
-  __shared__ __attribute__((aligned(16))) float zp[NC * PLANEP];
+  __shared__ __attribute__((aligned(16))) float zp[NC * PLANE];
+  __shared__ float fpart[NSLOT * R * NC];  // fold partials [slot][d][filter of the chunk], over chunks
   __shared__ double red[(NT / 64) * 5];
-  __shared__ int act_off[NS];    // compacted fold slots: z-plane offset of the 7x7 window,
-  __shared__ short act_slot[NS]; //                       the slot id
-  __shared__ char act_rows[NS];  //                       and the window rows / columns that lie
-  __shared__ char act_cols[NS];  //                       inside the z plane (at least 5 / 6)
-  __shared__ int wave_cnt[NT / 64];
   // taps of the current chunk, read by broadcast LDS loads so that the FMAs take them from VGPRs
   // (a VALU FMA with an SGPR operand issues at half rate on gfx950)
   constexpr int KAP = 52;                                   // padded adjoint tap stride (16 B rows)
@@ -236,47 +199,21 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     u6[idx] = uval;
   }
 
-  // ---- fold tiles: zero the z planes (frame stays zero) and compact the non-empty fold slots
-  int n_act = 0;
-  if (fold) {
-    float4* z4 = reinterpret_cast<float4*>(zp);
-    for (int i = tid; i < NC * PLANEP / 4; i += NT) z4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    bool act[2];
-    int off[2], nrow[2], ncol[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      int s = tid + h * NT, ply, plx, qy, qx;
-      act[h] = s < NS && slot_target<TW, TH>(s, x0, y0, H, W, ply, plx, qy, qx);
-      const int wr = qy - y0 + ZR, wc = qx - x0 + ZC;
-      off[h] = act[h] ? wr * W3P + wc : 0;
-      nrow[h] = min(KS, H3P - wr);
-      ncol[h] = min(KS, W3P - wc);
-    }
-    const int lane = tid & 63, wave = tid >> 6;
-    int base = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      unsigned long long m = __ballot(act[h]);
-      if (lane == 0) wave_cnt[wave] = __popcll(m);
-      __syncthreads();
-      int before = 0, total = 0;
-      for (int w = 0; w < NT / 64; ++w) {
-        int cw = wave_cnt[w];
-        before += w < wave ? cw : 0;
-        total += cw;
-      }
-      int pos = base + before + __popcll(m & ((1ull << lane) - 1ull));
-      if (act[h]) {
-        act_off[pos] = off[h];
-        act_slot[pos] = (short)(tid + h * NT);
-        act_rows[pos] = (char)nrow[h];
-        act_cols[pos] = (char)ncol[h];
-      }
-      base += total;
-      __syncthreads();
-    }
-    n_act = base;
-  }
+  // ---- fold tiles: clear the fold partials and count the fold items: positions
+  // along each live edge (y edges: TW columns; x edges: TH rows + the corner rows whose target row
+  // lies in the tile) times NC filters, filter index fastest
+  const bool e_ylo = fold && y0 == 0, e_yhi = fold && y0 + TH >= H - (R - 1);
+  const bool e_xlo = fold && x0 == 0, e_xhi = fold && x0 + TW >= W - (R - 1);
+  const int c_lo = y0 == 0 ? R : 0;                               // low-corner rows i = 0..2
+  const int c_h0 = max(0, H - y0 - TH), c_h1 = min(R - 1, H - 1 - y0);  // high-corner rows i
+  const int c_hn = e_yhi ? max(0, c_h1 - c_h0 + 1) : 0;
+  const int npx = TH + c_lo + c_hn;
+  const int f_s1 = e_ylo ? NC * TW : 0;                 // item starts of the y-high, x-low, x-high
+  const int f_s2 = f_s1 + (e_yhi ? NC * TW : 0);        // edges, and the item count
+  const int f_s3 = f_s2 + (e_xlo ? NC * npx : 0);
+  const int n_items = f_s3 + (e_xhi ? NC * npx : 0);
+  if (fold)
+    for (int i = tid; i < NSLOT * R * NC; i += NT) fpart[i] = 0.0f;
 
   // forward positions of this thread (fixed across chunks)
   int fbase[PPT];      // u6 offset of the window's top-left sample, or -1 when the slot is empty
@@ -289,7 +226,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     int gy = y0 - R + r, gx = x0 - R + c;
     bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
     fbase[k] = idx < PLANE3 ? r * W6 + c : -1;
-    zofs[k] = (r + ZR) * W3P + c + ZC;
+    zofs[k] = r * W3 + c;
     flive[k] = idx < PLANE3 && (inimg || bc == PERIODIC);
     fown[k] = idx < PLANE3 && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
   }
@@ -304,18 +241,6 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   for (int i = 0; i < BR; ++i)
 #pragma unroll
     for (int j = 0; j < BC; ++j) acc[i][j] = 0.0f;
-  float sacc[SLOTS_PT];
-  int s_off[SLOTS_PT], s_nr[SLOTS_PT], s_nc[SLOTS_PT];
-  bool s_live[SLOTS_PT];
-#pragma unroll
-  for (int k = 0; k < SLOTS_PT; ++k) {
-    const int m = min(lt + k * GT, NS - 1);
-    sacc[k] = 0.0f;
-    s_live[k] = lt + k * GT < n_act;
-    s_off[k] = s_live[k] ? act_off[m] : 0;
-    s_nr[k] = s_live[k] ? act_rows[m] : KS;
-    s_nc[k] = s_live[k] ? act_cols[m] : KS;
-  }
 
   __syncthreads();
 
@@ -343,7 +268,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) zv[j] = flive[k] && j < ncur ? src[(size_t)j * a.zstride] : 0.0f;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) zp[j * PLANEP + zofs[k]] = zv[j];
+        for (int j = 0; j < NC; ++j) zp[j * PLANE + zofs[k]] = zv[j];
       }
     } else if constexpr (FWD == FWD_MFMA_BF16) {
       // ---- stage 2 (matrix cores, BF16 operands, FP32 accumulation): v_mfma_f32_16x16x32_bf16 with
@@ -401,7 +326,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
         const bool live = inr && (inimg || bc == PERIODIC);
         const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
-        const int zo = (r + ZR) * W3P + c + ZC;
+        const int zo = r * W3 + c;
         // the position's u(p) is the same for the 4 filters of this lane; fetch it per lane
         float e = 0.0f;
 #pragma unroll
@@ -409,7 +334,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           const float yv = fmaf(uc, ksum[j], acc4[j]);
           const float den = fmaf(yv, yv, 1.0f);
           const float z = thv[j] * 2.0f * yv * fast_rcp(den);
-          if (inr) zp[(4 * lk + j) * PLANEP + zo] = live ? z : 0.0f;
+          if (inr) zp[(4 * lk + j) * PLANE + zo] = live ? z : 0.0f;
           if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
             a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
           e = fmaf(thv[j], fast_log(den), e);
@@ -462,14 +387,14 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
           const bool live = inr && (inimg || bc == PERIODIC);
           const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
-          const int zo = (r + ZR) * W3P + c + ZC;
+          const int zo = r * W3 + c;
           float e = 0.0f;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const float yv = acc2[h][j];
             const float den = fmaf(yv, yv, 1.0f);
             const float z = thv[j] * 2.0f * yv * fast_rcp(den);
-            if (inr) zp[(4 * lk + j) * PLANEP + zo] = live ? z : 0.0f;
+            if (inr) zp[(4 * lk + j) * PLANE + zo] = live ? z : 0.0f;
             if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
               a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
             e = fmaf(thv[j], fast_log(den), e);
@@ -520,7 +445,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           float th = j < ncur ? a.theta[c0 + j] : 0.0f;
           float den = fmaf(y[k][j], y[k][j], 1.0f);
           float z = th * 2.0f * y[k][j] * fast_rcp(den);
-          zp[j * PLANEP + zofs[k]] = flive[k] ? z : 0.0f;
+          zp[j * PLANE + zofs[k]] = flive[k] ? z : 0.0f;
           if (UNF == FWD_HALF && fown[k] && j < ncur) {
             const int idx = tid + k * NT, r = idx / W3, c = idx - r * W3;
             a.zbuf[(size_t)(c0 + j) * a.zstride + im.off + (size_t)(y0 - R + r) * W + (x0 - R + c)] = z;
@@ -533,8 +458,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     __syncthreads();
 
     // ---- stage 3: adjoint bank.  Per filter of the group: the BR x BC block of this thread from a
-    // (BR+6) x (BC+6) window in registers; then, on fold tiles, the fold slots assigned to this
-    // thread (7x7 windows around extended samples, the same 49 taps).
+    // (BR+6) x (BC+6) window in registers; then, on fold tiles, the fold items of the chunk.
 #pragma unroll 1
     for (int jj = 0; jj < (UNF == FWD_HALF ? 0 : FPG); ++jj) {
       const int j = grp * FPG + jj;
@@ -545,15 +469,15 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         float4 q4 = *reinterpret_cast<const float4*>(ka_s + j * KAP + t);
         kt[t] = q4.x; kt[t + 1] = q4.y; kt[t + 2] = q4.z; kt[t + 3] = q4.w;
       }
-      const float* zplane = zp + j * PLANEP;
-      const float* zb = zplane + (row0 + ZR) * W3P + col0 + ZC;
+      const float* zplane = zp + j * PLANE;
+      const float* zb = zplane + row0 * W3 + col0;
       // stream the (BR+6) x (BC+6) window one row at a time; row q feeds output rows q - ta
 #pragma unroll
       for (int q = 0; q < WR; ++q) {
         float wrow[WC];
 #pragma unroll
         for (int s = 0; s < WC; s += 2) {
-          float2 v2 = *reinterpret_cast<const float2*>(zb + q * W3P + s);
+          float2 v2 = *reinterpret_cast<const float2*>(zb + q * W3 + s);
           wrow[s] = v2.x;
           wrow[s + 1] = v2.y;
         }
@@ -568,69 +492,87 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         }
       }
     }
-    // the fold slots of this thread, filter by filter, in a pass of their own so that the window
-    // loads of the regular blocks and of the slots do not compete for registers
+    // the fold items of this thread (all threads take part; a pass of its own after the regular
+    // blocks, whose window registers are dead by then).  Each item owns its 3 partials.
     if (fold) {
 #pragma unroll 1
-      for (int jj = 0; jj < FPG; ++jj) {
-        const int j = grp * FPG + jj;
-        if (j >= ncur) break;
-        float kt[KAP];
+      for (int it = tid; it < n_items; it += NT) {
+        const int e = (it >= f_s1) + (it >= f_s2) + (it >= f_s3);   // 0 y-low 1 y-high 2 x-low 3 x-high
+        const int loc = it - (e == 0 ? 0 : e == 1 ? f_s1 : e == 2 ? f_s2 : f_s3);
+        const int j = loc & (NC - 1), p = loc / NC;
+        if (j >= ncur) continue;
+        const float* zpl = zp + j * PLANE;
+        const float* kj = ka_s + j * KAP;
+        float Z[R][KS], K[R][KS];
+        int slot;
+        if (e < 2) {
+          // y edge, position = tile column p: z lines are rows, taps run along a tap row
+          slot = e * TW + p;
+          const int zr0 = e == 0 ? R : H - 1 - y0 + R;           // plane row of the edge line
+          const float* zb = zpl + zr0 * W3 + p;                  // + t: column x0 + p - 3 + t
+          const int zls = e == 0 ? W3 : -W3;
+          const float* kb = kj + (e == 0 ? (R + 1) * KS : (R - 1) * KS);
+          const int kls = e == 0 ? KS : -KS;
 #pragma unroll
-        for (int t = 0; t < KAP; t += 4) {
-          float4 q4 = *reinterpret_cast<const float4*>(ka_s + j * KAP + t);
-          kt[t] = q4.x; kt[t + 1] = q4.y; kt[t + 2] = q4.z; kt[t + 3] = q4.w;
-        }
-        const float* zplane = zp + j * PLANEP;
+          for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int k = 0; k < SLOTS_PT; ++k) {
-          if (!s_live[k]) break;
-          const float* zw = zplane + s_off[k];
-          // branch-free: every load is issued unconditionally.  Window rows 5, 6 and column 6 that
-          // would leave the plane read the last in-plane row / column instead and are weighted zero
-          // (row and column offsets and weights are arithmetic, so no load waits behind a branch).
-          const int rofs5 = min(5, s_nr[k] - 1) * W3P, rofs6 = min(6, s_nr[k] - 1) * W3P;
-          const int cofs6 = min(6, s_nc[k] - 1);
-          const float m5 = (float)(s_nr[k] > 5), m6 = (float)(s_nr[k] > 6), mc6 = (float)(s_nc[k] > 6);
-          float v = 0.0f;
+            for (int t = 0; t < KS; ++t) {
+              Z[r][t] = zb[r * zls + t];
+              K[r][t] = kb[r * kls + t];
+            }
+        } else {
+          // x edge, position = extended row gy: z lines are columns, taps run down a tap column.
+          // Window rows outside the plane are off the image (rows < 0 for the low corners, >= H
+          // for the high ones); they read the plane's first / last row, which is off the image too.
+          const int q = p - TH;
+          const int gy = q < 0 ? y0 + p : (q < c_lo ? -1 - q : H + c_h0 + q - c_lo);
+          slot = 2 * TW + (e - 2) * NPX + (q < 0 ? p : (q < c_lo ? TH + q : TH + R + c_h0 + q - c_lo));
+          const int zc0 = e == 2 ? R : W - 1 - x0 + R;            // plane column of the edge line
+          const float* zb = zpl + zc0;
+          const int zls = e == 2 ? 1 : -1;
+          const float* kb = kj + (e == 2 ? R + 1 : R - 1);
+          const int kls = e == 2 ? 1 : -1;
+          const int prow = gy - y0;                                // plane row of window row 0
 #pragma unroll
-          for (int ta = 0; ta < KS; ++ta) {
-            const float* zr = zw + (ta < 5 ? ta * W3P : (ta == 5 ? rofs5 : rofs6));
-            const float mr = ta < 5 ? 1.0f : (ta == 5 ? m5 : m6);
+          for (int t = 0; t < KS; ++t) {
+            const int ro = min(max(prow + t, 0), H3 - 1) * W3;
 #pragma unroll
-            for (int tb = 0; tb < KS; ++tb) {
-              const float w = tb < 6 ? kt[ta * KS + tb] : kt[ta * KS + tb] * mc6;
-              v = fmaf(ta < 5 ? w : w * mr, zr[tb < 6 ? tb : cofs6], v);
+            for (int r = 0; r < R; ++r) {
+              Z[r][t] = zb[ro + r * zls];
+              K[r][t] = kb[r * kls + t * KS];
             }
           }
-          sacc[k] += v;
         }
+        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+          v0 = fmaf(K[0][t], Z[0][t], v0);
+          v0 = fmaf(K[1][t], Z[1][t], v0);
+          v0 = fmaf(K[2][t], Z[2][t], v0);
+          v1 = fmaf(K[1][t], Z[0][t], v1);
+          v1 = fmaf(K[2][t], Z[1][t], v1);
+          v2 = fmaf(K[2][t], Z[0][t], v2);
+        }
+        float* fo = fpart + slot * R * NC + j;
+        fo[0] += v0;
+        fo[NC] += v1;
+        fo[2 * NC] += v2;
       }
     }
     __syncthreads();
   }
 
-  // ---- epilogue: combine groups and fold slots in a fixed order, chain rule, store
+  // ---- epilogue: combine groups and mirror terms in a fixed order, chain rule, store
   if constexpr (UNF == FWD_HALF) {
     double v[5] = {accF, accG, accS1, accS2, accM};
     block_partials<NT, 5>(v, red, a.partials);
     return;
   }
   float* gsum = zp;                       // [NG][TH][TW]
-  float* slots = zp + NG * TH * TW;       // [NG][NS]
 #pragma unroll
   for (int i = 0; i < BR; ++i)
 #pragma unroll
     for (int jx = 0; jx < BC; ++jx) gsum[grp * TH * TW + (row0 + i) * TW + col0 + jx] = acc[i][jx];
-  if (fold) {
-    for (int i = tid; i < NG * NS; i += NT) slots[i] = 0.0f;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < SLOTS_PT; ++k) {
-      const int m = lt + k * GT;
-      if (m < n_act) slots[grp * NS + act_slot[m]] = sacc[k];
-    }
-  }
   __syncthreads();
   for (int idx = tid; idx < TH * TW; idx += NT) {
     int i = idx / TW, jx = idx - i * TW;
@@ -640,19 +582,23 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
 #pragma unroll
     for (int q = 0; q < NG; ++q) g += gsum[q * TH * TW + idx];
     if (fold) {
-      const int cb = 6 * TW + 6 * TH;
+      // mirror terms of this pixel (edges, then corners), each summed over the NC filter partials
+      // in filter order; a pixel of an image 4 or 5 wide lies within 3 of both opposite edges
+      const int dyl = py, dyh = H - 1 - py, dxl = px, dxh = W - 1 - px;
+      const int xl = 2 * TW, xh = 2 * TW + NPX;
+      auto add = [&](int slot, int d) {
+        const float* fp = fpart + (slot * R + d) * NC;
 #pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        const float* sl = slots + q * NS;
-        if (py < R) g += sl[py * TW + jx];
-        if (py >= H - R) g += sl[3 * TW + (H - 1 - py) * TW + jx];
-        if (px < R) g += sl[6 * TW + px * TH + i];
-        if (px >= W - R) g += sl[6 * TW + 3 * TH + (W - 1 - px) * TH + i];
-        if (py < R && px < R) g += sl[cb + 0 * 9 + py * 3 + px];
-        if (py < R && px >= W - R) g += sl[cb + 1 * 9 + py * 3 + (W - 1 - px)];
-        if (py >= H - R && px < R) g += sl[cb + 2 * 9 + (H - 1 - py) * 3 + px];
-        if (py >= H - R && px >= W - R) g += sl[cb + 3 * 9 + (H - 1 - py) * 3 + (W - 1 - px)];
-      }
+        for (int jj = 0; jj < NC; ++jj) g += fp[jj];
+      };
+      if (dyl < R) add(jx, dyl);
+      if (dyh < R) add(TW + jx, dyh);
+      if (dxl < R) add(xl + i, dxl);
+      if (dxh < R) add(xh + i, dxh);
+      if (dxl < R && dyl < R) add(xl + TH + dyl, dxl);
+      if (dxl < R && dyh < R) add(xl + TH + R + dyh, dxl);
+      if (dxh < R && dyl < R) add(xh + TH + dyl, dxh);
+      if (dxh < R && dyh < R) add(xh + TH + R + dyh, dxh);
     }
     if (logm) g *= u6[(i + 2 * R) * W6 + jx + 2 * R];
     go[(size_t)py * W + px] = g;
