@@ -52,13 +52,14 @@ struct FusedArgs {
 template <int NT, int NV>
 __device__ __forceinline__ void block_partials(double (&v)[NV], double* red, double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the NV chains are independent: step them together so that their cross-lane latencies overlap
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double x = v[k];
+  for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) red[wave * NV + k] = x;
-  }
+    for (int k = 0; k < NV; ++k) v[k] += __shfl_down(v[k], off, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
   __syncthreads();
   if (threadIdx.x < NV) {
     double s = 0.0;
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   static_assert(NG * TH * TW <= NC * PLANE, "epilogue does not fit in the z buffer");
   static_assert((NC & (NC - 1)) == 0 && TH >= R && TW >= R, "fold items: NC a power of two, tiles >= 3");
   static_assert(FWD == FWD_VALU || NC == 16, "the MFMA forwards take one 16-filter block per chunk");
+  static_assert(KK % 4 == 1, "the FP32 matrix-core forward takes taps 0 .. KK - 2 in steps of 4");
   constexpr int NGROUP = (PLANE3 + 15) / 16;      // MFMA forward: groups of 16 consecutive positions
 
   __shared__ float u6[H6 * W6];
@@ -343,64 +345,60 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       }
     } else if constexpr (FWD == FWD_MFMA_F32) {
       // ---- stage 2 (matrix cores): per group of 16 consecutive R3 positions,
-      // Y^T[16 filters x 16 positions] = Kflip^T[16 x 52 taps] . X[52 taps x 16 positions] with
-      // v_mfma_f32_16x16x4f32 (taps 49..51 carry zero weight).  Lane (m = lane % 16, k = lane / 16)
-      // holds the A value Kflip[filter m][tap 4s + k] and the B value u6 at tap 4s + k of position m;
-      // the result lands as y for position m, filters 4k .. 4k + 3.
+      // Y^T[16 filters x 16 positions] = Kflip^T[16 x 48 taps] . X[48 taps x 16 positions] with
+      // twelve v_mfma_f32_16x16x4f32, and the last tap (48) added on the VALU.  Lane (m = lane % 16,
+      // k = lane / 16) holds the A value Kflip[filter m][tap 4s + k] and the B value u6 at tap 4s + k of
+      // position m; the result lands as y for position m, filters 4k .. 4k + 3.
       const int lane = tid & 63, wave = tid >> 6, lm = lane & 15, lk = lane >> 4;
-      float a_reg[13];
-      int toff[13];
+      constexpr int NS4 = KK / 4;                  // 12 MFMA steps of 4 taps; KK = 4 NS4 + 1
+      float a_reg[NS4];
+      int toff[NS4];
 #pragma unroll
-      for (int s = 0; s < 13; ++s) {
+      for (int s = 0; s < NS4; ++s) {
         const int t = 4 * s + lk;
-        a_reg[s] = t < KK ? kf_s[t * NC + lm] : 0.0f;
-        toff[s] = t < KK ? (t / KS) * W6 + (t % KS) : 0;
+        a_reg[s] = kf_s[t * NC + lm];
+        toff[s] = (t / KS) * W6 + (t % KS);
       }
+      const float4 klast = *reinterpret_cast<const float4*>(kf_s + (KK - 1) * NC + 4 * lk);  // tap 48, filters 4k..
+      constexpr int TLAST = (KS - 1) * W6 + (KS - 1);
       float thv[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) thv[j] = 4 * lk + j < ncur ? a.theta[c0 + 4 * lk + j] : 0.0f;
-      // two position groups per pass: two independent accumulator chains keep the matrix pipe busy
-      // while each MFMA waits for its predecessor
+      // one position group per pass: with four waves per SIMD the other waves' chains fill the
+      // matrix pipe while this one waits for its predecessor
 #pragma unroll 1
-      for (int g0 = wave; g0 < NGROUP; g0 += 2 * (NT / 64)) {
-        int pb2[2], rr[2], cc[2];
-        bool inr2[2];
+      for (int g = wave; g < NGROUP; g += NT / 64) {
+        const int p = g * 16 + lm;
+        const bool inr = p < PLANE3;
+        const int r = inr ? p / W3 : 0, c = inr ? p - (p / W3) * W3 : 0;
+        const int pbase = r * W6 + c;
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int p = (g0 + h * (NT / 64)) * 16 + lm;
-          inr2[h] = p < PLANE3;
-          rr[h] = inr2[h] ? p / W3 : 0;
-          cc[h] = inr2[h] ? p - rr[h] * W3 : 0;
-          pb2[h] = rr[h] * W6 + cc[h];
+        for (int s = 0; s < NS4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a_reg[s], u6[pbase + toff[s]], acc, 0, 0, 0);
+        const float ulast = u6[pbase + TLAST];
+        acc[0] = fmaf(klast.x, ulast, acc[0]);
+        acc[1] = fmaf(klast.y, ulast, acc[1]);
+        acc[2] = fmaf(klast.z, ulast, acc[2]);
+        acc[3] = fmaf(klast.w, ulast, acc[3]);
+        const int gy = y0 - R + r, gx = x0 - R + c;
+        const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+        // lanes past the last position computed position 0 (r = c = 0) and store its value there
+        // again: the same bits as the lane that owns it, so the duplicate store is harmless
+        const bool live = inimg || bc == PERIODIC;
+        const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
+        const int zo = r * W3 + c;
+        float e = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float yv = acc[j];
+          const float den = fmaf(yv, yv, 1.0f);
+          const float z = thv[j] * 2.0f * yv * fast_rcp(den);
+          zp[(4 * lk + j) * PLANE + zo] = live ? z : 0.0f;
+          if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
+            a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
+          e = fmaf(thv[j], fast_log(den), e);
         }
-        floatx4 acc2[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
-#pragma unroll
-        for (int s = 0; s < 13; ++s)
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            acc2[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_reg[s], u6[pb2[h] + toff[s]], acc2[h], 0, 0, 0);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int r = rr[h], c = cc[h];
-          const bool inr = inr2[h];
-          const int gy = y0 - R + r, gx = x0 - R + c;
-          const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-          const bool live = inr && (inimg || bc == PERIODIC);
-          const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
-          const int zo = r * W3 + c;
-          float e = 0.0f;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float yv = acc2[h][j];
-            const float den = fmaf(yv, yv, 1.0f);
-            const float z = thv[j] * 2.0f * yv * fast_rcp(den);
-            if (inr) zp[(4 * lk + j) * PLANE + zo] = live ? z : 0.0f;
-            if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
-              a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
-            e = fmaf(thv[j], fast_log(den), e);
-          }
-          if (own) accF += (double)e;
-        }
+        if (own) accF += (double)e;
       }
     } else {
       // ---- stage 2: forward bank on tile + 3 halo; one row of taps of 8 filters (in SGPRs) per pass
