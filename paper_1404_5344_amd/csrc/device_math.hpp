@@ -4,6 +4,30 @@
 
 namespace foe {
 
+// One step of wave_sum_f64: v + (v moved by the DPP pattern CTRL; 0 where the pattern has no source
+// or ROW_MASK leaves the row out).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of x over the 64 lanes of a wave, left in lane 63 (the other lanes hold partial sums): an
+// inclusive scan with DPP moves, row shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the
+// broadcasts of lane 15 of each row into the next row and of lane 31 into rows 2 and 3.  Register
+// moves only (no LDS crossbar); the order of the additions is fixed.
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  x = dpp_add_f64<0x111, 0xf>(x);   // row_shr:1
+  x = dpp_add_f64<0x112, 0xf>(x);   // row_shr:2
+  x = dpp_add_f64<0x114, 0xf>(x);   // row_shr:4
+  x = dpp_add_f64<0x118, 0xf>(x);   // row_shr:8
+  x = dpp_add_f64<0x142, 0xa>(x);   // row_bcast:15 -> rows 1, 3
+  x = dpp_add_f64<0x143, 0xc>(x);   // row_bcast:31 -> rows 2, 3
+  return x;
+}
+
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // e^x through the hardware 2^x
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }

@@ -59,10 +59,8 @@ __device__ __forceinline__ void decide_block(DevState* st, const double* __restr
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0 && wave < 4) red[wave][k] = x;
+    const double x = wave_sum_f64(v[k]);
+    if (lane == 63 && wave < 4) red[wave][k] = x;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;

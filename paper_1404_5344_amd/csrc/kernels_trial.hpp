@@ -52,12 +52,9 @@ struct FusedArgs {
 template <int NT, int NV>
 __device__ __forceinline__ void block_partials(double (&v)[NV], double* red, double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // the NV chains are independent: step them together so that their cross-lane latencies overlap
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += __shfl_down(v[k], off, 64);
-  if (lane == 0)
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_f64(v[k]);
+  if (lane == 63)
 #pragma unroll
     for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
   __syncthreads();
