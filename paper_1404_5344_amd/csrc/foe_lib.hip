@@ -475,7 +475,7 @@ foe_status create_common(const foe_params* p, int n_img, const int32_t* H, const
     for (int a = 0; a < KS; ++a)
       for (int b = 0; b < KS; ++b) {
         float k = filters_host[(size_t)i * KK + a * KS + b];
-        ka[i * KK + a * KS + b] = k;
+        ka[i * KK + a * KS + b] = (float)(2.0 * (double)th[i] * (double)k);   // 2 theta_i k_i: z planes hold y/(1+y^2)
         const int c = i / V_NC, j = i % V_NC, t = (KS - 1 - a) * KS + (KS - 1 - b);
         kf[((size_t)c * KK + t) * V_NC + j] = k;
       }

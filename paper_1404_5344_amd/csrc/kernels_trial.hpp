@@ -5,15 +5,17 @@
 //      (x+ = prox_{aG}(x - a grad F(x) + b (x - x_prev)), Sec. II-C, eq. (fplusg)),
 //      then u+ = e^{x+} (log models) into LDS;
 //   2. per chunk of NC filters: the forward bank y_i = K_i u+ on the tile + 3 halo,
-//      z_i = theta_i rho'(y_i) into LDS, and theta_i rho(y_i) summed over the tile
+//      z_i = y_i / (1 + y_i^2) = rho'(y_i) / 2 into LDS, and theta_i rho(y_i) summed over the tile
 //      (F(x+), Sec. II-A, eq. (FOEmodel));
-//   3. per chunk: the adjoint bank sum_i K_i^T z_i on the tile (correlation with k_i,
-//      Sec. II-C), plus the mirror terms of the SYMMETRIC boundary map;
+//   3. per chunk: the adjoint bank sum_i theta_i K_i^T rho'(y_i) = sum_i K_i^T z_i with the taps
+//      scaled by 2 theta_i (correlation, Sec. II-C), plus the mirror terms of the SYMMETRIC map;
 //   4. the chain rule grad_w F = u .* sum_i K_i^T z_i, written as the gradient at x+
 //      for the next iteration (speculative: used only if the trial is accepted),
 //      and per-block partial sums {F(x+), G(x+), <grad F(x), d>, |d|^2, |x - x_prev|^2}.
 // In EVAL mode stage 1 is the identity (x+ = x_in): F, G and grad F at x_in.
 #pragma once
+#include <type_traits>
+
 #include "device_math.hpp"
 
 namespace foe {
@@ -41,7 +43,7 @@ struct FusedArgs {
   double* partials;                     // [gridDim.x][PART_COLS]
   const float* kf;                      // forward taps, flipped and chunk-transposed:
                                         //   kf[(c * KK + a * 7 + b) * NC + j] = k_{c*NC+j}[6-a][6-b]
-  const float* ka;                      // adjoint taps: ka[i][a][b] = k_i[a][b]
+  const float* ka;                      // adjoint taps: ka[i][a][b] = 2 theta_i k_i[a][b]
   const float* theta;
   float* zbuf;                          // unfused z planes: zbuf[i * zstride + off + y * W + x]
   long long zstride;
@@ -63,6 +65,72 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* red, dou
     for (int w = 0; w < NT / 64; ++w) s += red[w * NV + threadIdx.x];
     out[(size_t)blockIdx.x * PART_COLS + threadIdx.x] = s;
   }
+}
+
+// One chunk of the FP32 matrix-core forward bank on the R3 region of a TW x TH tile: the position
+// groups g0, g0 + GS, ... (16 consecutive positions each, GS groups apart).  Per group, twelve
+// v_mfma_f32_16x16x4f32 take taps 0..47 (lane (m, k): A = filter m at tap 4s + k, B = u6 at tap
+// 4s + k of position m) and the VALU adds tap 48; lane (m, k) then holds y for position m, filters
+// 4k .. 4k + 3, and stores z = y / (1 + y^2) into the z planes.  Returns this thread's sum of
+// theta ln(1 + y^2) over its own (tile, in-image) positions.  ALL_IN: every R3 position lies in the
+// image, so that no z needs masking and every tile position is an own one.  FUSION == FWD_HALF also stores z of
+// the own positions to HBM (zb = plane of the chunk's first filter at the image, zstride apart).
+// Lanes past the last position compute position 0 and store its value there again: the same bits
+// as the lane that owns it, so the duplicate store is harmless.
+template <int TW, int TH, int NC, int GS, int FUSION, bool ALL_IN>
+__device__ __forceinline__ float mfma_forward_chunk(const float* u6, float* zp, const float (&a_reg)[KK / 4],
+                                                    const int (&toff)[KK / 4], float4 klast, const float (&thl)[4], int g0, int lm, int lk, int y0, int x0,
+                                                    int H, int W, bool periodic, float* zb, long long zstride, int nlive) {
+  constexpr int W6 = TW + 4 * R, W3 = TW + 2 * R, H3 = TH + 2 * R, PLANE = H3 * W3;
+  constexpr int NGROUP = (PLANE + 15) / 16;
+  constexpr int STEP = GS * 16, DR = STEP / W3, DC = STEP % W3;   // position advance per pass
+  constexpr int TLAST = (KS - 1) * W6 + (KS - 1);
+  constexpr int NFULL = PLANE / 16;                               // groups with no position past the plane
+  int p = g0 * 16 + lm, r = p / W3, c = p - r * W3;
+  float ef = 0.0f;
+  // one group: PARTIAL = the last group, whose lanes past the plane take position 0
+  auto group = [&](auto partial_tag) {
+    constexpr bool PARTIAL = decltype(partial_tag)::value;
+    const bool inr = !PARTIAL || p < PLANE;
+    const int rr = inr ? r : 0, cc = inr ? c : 0, zo = inr ? p : 0;
+    const int pbase = rr * W6 + cc;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < KK / 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a_reg[s], u6[pbase + toff[s]], acc, 0, 0, 0);
+    const float ulast = u6[pbase + TLAST];
+    acc[0] = fmaf(klast.x, ulast, acc[0]);
+    acc[1] = fmaf(klast.y, ulast, acc[1]);
+    acc[2] = fmaf(klast.z, ulast, acc[2]);
+    acc[3] = fmaf(klast.w, ulast, acc[3]);
+    const int gy = y0 - R + rr, gx = x0 - R + cc;
+    bool inimg = true;
+    if constexpr (!ALL_IN) inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+    const bool live = ALL_IN || inimg || periodic;
+    const bool own = inr && inimg && (unsigned)(rr - R) < (unsigned)TH && (unsigned)(cc - R) < (unsigned)TW;
+    float e = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float yv = acc[j];
+      const float den = fmaf(yv, yv, 1.0f);
+      const float z = yv * fast_rcp(den);
+      zp[(4 * lk + j) * PLANE + zo] = live ? z : 0.0f;
+      if (FUSION == FWD_HALF && own && 4 * lk + j < nlive) zb[(4 * lk + j) * zstride + (long long)gy * W + gx] = z;
+      e = fmaf(thl[j], __builtin_amdgcn_logf(den), e);   // theta ln 2 * log2(1 + y^2)
+    }
+    ef += own ? e : 0.0f;
+    p += STEP;
+    c += DC;
+    r += DR;
+    if (c >= W3) {
+      c -= W3;
+      r += 1;
+    }
+  };
+  int g = g0;
+#pragma unroll 1
+  for (; g < NFULL; g += GS) group(std::false_type{});
+  if (NFULL < NGROUP && g < NGROUP) group(std::true_type{});
+  return ef;
 }
 
 // Mirror terms of the SYMMETRIC boundary map (half-sample reflection, so x(-1-i) = x(i)).  The
@@ -151,6 +219,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   }
   const float* __restrict__ f = a.f + im.off;
   const bool fold = UNF != FWD_HALF && bc == SYMMETRIC && (y0 < R || y0 + TH > H - R || x0 < R || x0 + TW > W - R);
+  // every R3 position (tile + 3) in the image: z needs no mask, every tile position is an own one
+  const bool all_in = y0 >= R && y0 + TH + R <= H && x0 >= R && x0 + TW + R <= W;
 
   double accF = 0.0, accG = 0.0, accS1 = 0.0, accS2 = 0.0, accM = 0.0;
 
@@ -332,7 +402,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         for (int j = 0; j < 4; ++j) {
           const float yv = fmaf(uc, ksum[j], acc4[j]);
           const float den = fmaf(yv, yv, 1.0f);
-          const float z = thv[j] * 2.0f * yv * fast_rcp(den);
+          const float z = yv * fast_rcp(den);
           if (inr) zp[(4 * lk + j) * PLANE + zo] = live ? z : 0.0f;
           if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
             a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
@@ -354,49 +424,24 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       for (int s = 0; s < NS4; ++s) {
         const int t = 4 * s + lk;
         a_reg[s] = kf_s[t * NC + lm];
-        toff[s] = (t / KS) * W6 + (t % KS);
+        // taps 4s + k and 4(s + 7) + k are 28 = 4 KS apart: 4 rows of u6 in every lane, so that the
+        // loads of steps s and s + 7 share an address register (the difference is an immediate)
+        toff[s] = s < KS ? (t / KS) * W6 + (t % KS) : toff[s - KS] + 4 * W6;
       }
       const float4 klast = *reinterpret_cast<const float4*>(kf_s + (KK - 1) * NC + 4 * lk);  // tap 48, filters 4k..
-      constexpr int TLAST = (KS - 1) * W6 + (KS - 1);
-      float thv[4];
+      float thl[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) thv[j] = 4 * lk + j < ncur ? a.theta[c0 + 4 * lk + j] : 0.0f;
+      for (int j = 0; j < 4; ++j) thl[j] = (4 * lk + j < ncur ? a.theta[c0 + 4 * lk + j] : 0.0f) * 0.6931471805599453f;
       // one position group per pass: with four waves per SIMD the other waves' chains fill the
       // matrix pipe while this one waits for its predecessor
-#pragma unroll 1
-      for (int g = wave; g < NGROUP; g += NT / 64) {
-        const int p = g * 16 + lm;
-        const bool inr = p < PLANE3;
-        const int r = inr ? p / W3 : 0, c = inr ? p - (p / W3) * W3 : 0;
-        const int pbase = r * W6 + c;
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < NS4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a_reg[s], u6[pbase + toff[s]], acc, 0, 0, 0);
-        const float ulast = u6[pbase + TLAST];
-        acc[0] = fmaf(klast.x, ulast, acc[0]);
-        acc[1] = fmaf(klast.y, ulast, acc[1]);
-        acc[2] = fmaf(klast.z, ulast, acc[2]);
-        acc[3] = fmaf(klast.w, ulast, acc[3]);
-        const int gy = y0 - R + r, gx = x0 - R + c;
-        const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-        // lanes past the last position computed position 0 (r = c = 0) and store its value there
-        // again: the same bits as the lane that owns it, so the duplicate store is harmless
-        const bool live = inimg || bc == PERIODIC;
-        const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
-        const int zo = r * W3 + c;
-        float e = 0.0f;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float yv = acc[j];
-          const float den = fmaf(yv, yv, 1.0f);
-          const float z = thv[j] * 2.0f * yv * fast_rcp(den);
-          zp[(4 * lk + j) * PLANE + zo] = live ? z : 0.0f;
-          if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
-            a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
-          e = fmaf(thv[j], fast_log(den), e);
-        }
-        if (own) accF += (double)e;
-      }
+      float* zb = UNF == FWD_HALF ? a.zbuf + (size_t)c0 * a.zstride + im.off : nullptr;
+      const float ef = all_in ? mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, true>(
+                                      u6, zp, a_reg, toff, klast, thl, wave, lm, lk, y0, x0, H, W,
+                                      bc == PERIODIC, zb, a.zstride, ncur)
+                                : mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, false>(
+                                      u6, zp, a_reg, toff, klast, thl, wave, lm, lk, y0, x0, H, W,
+                                      bc == PERIODIC, zb, a.zstride, ncur);
+      accF += (double)ef;
     } else {
       // ---- stage 2: forward bank on tile + 3 halo; one row of taps of 8 filters (in SGPRs) per pass
       float y[PPT][NC];
@@ -439,7 +484,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         for (int j = 0; j < NC; ++j) {
           float th = j < ncur ? a.theta[c0 + j] : 0.0f;
           float den = fmaf(y[k][j], y[k][j], 1.0f);
-          float z = th * 2.0f * y[k][j] * fast_rcp(den);
+          float z = y[k][j] * fast_rcp(den);
           zp[j * PLANE + zofs[k]] = flive[k] ? z : 0.0f;
           if (UNF == FWD_HALF && fown[k] && j < ncur) {
             const int idx = tid + k * NT, r = idx / W3, c = idx - r * W3;
