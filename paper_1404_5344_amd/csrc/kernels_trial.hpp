@@ -67,6 +67,33 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* red, dou
   }
 }
 
+// The three mirror terms of one fold item from its z lines and tap lines (see the mirror-term comment
+// below): Z_r = zb + r zls + t ZT, K_m = kb + m kls + t KT for t = 0..6; v(d) = sum_{r <= 2 - d}
+// <K_{d+r}, Z_r>.  The strides along the lines are template constants so that every load of a
+// line takes an immediate offset from one address register.
+template <int ZT, int KT>
+__device__ __forceinline__ void fold_lines(const float* zb, int zls, const float* kb, int kls, float& v0, float& v1,
+                                           float& v2) {
+  float Z[R][KS], K[R][KS];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      Z[r][t] = zb[r * zls + t * ZT];
+      K[r][t] = kb[r * kls + t * KT];
+    }
+  v0 = v1 = v2 = 0.0f;
+#pragma unroll
+  for (int t = 0; t < KS; ++t) {
+    v0 = fmaf(K[0][t], Z[0][t], v0);
+    v0 = fmaf(K[1][t], Z[1][t], v0);
+    v0 = fmaf(K[2][t], Z[2][t], v0);
+    v1 = fmaf(K[1][t], Z[0][t], v1);
+    v1 = fmaf(K[2][t], Z[1][t], v1);
+    v2 = fmaf(K[2][t], Z[0][t], v2);
+  }
+}
+
 // One chunk of the FP32 matrix-core forward bank on the R3 region of a TW x TH tile: the position
 // groups g0, g0 + GS, ... (16 consecutive positions each, GS groups apart).  Per group, twelve
 // v_mfma_f32_16x16x4f32 take taps 0..47 (lane (m, k): A = filter m at tap 4s + k, B = u6 at tap
@@ -543,55 +570,53 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         if (j >= ncur) continue;
         const float* zpl = zp + j * PLANE;
         const float* kj = ka_s + j * KAP;
-        float Z[R][KS], K[R][KS];
+        float v0, v1, v2;
         int slot;
         if (e < 2) {
           // y edge, position = tile column p: z lines are rows, taps run along a tap row
           slot = e * TW + p;
           const int zr0 = e == 0 ? R : H - 1 - y0 + R;           // plane row of the edge line
-          const float* zb = zpl + zr0 * W3 + p;                  // + t: column x0 + p - 3 + t
-          const int zls = e == 0 ? W3 : -W3;
-          const float* kb = kj + (e == 0 ? (R + 1) * KS : (R - 1) * KS);
-          const int kls = e == 0 ? KS : -KS;
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int t = 0; t < KS; ++t) {
-              Z[r][t] = zb[r * zls + t];
-              K[r][t] = kb[r * kls + t];
-            }
+          fold_lines<1, 1>(zpl + zr0 * W3 + p, e == 0 ? W3 : -W3,  // + t: column x0 + p - 3 + t
+                           kj + (e == 0 ? (R + 1) * KS : (R - 1) * KS), e == 0 ? KS : -KS, v0, v1, v2);
         } else {
-          // x edge, position = extended row gy: z lines are columns, taps run down a tap column.
-          // Window rows outside the plane are off the image (rows < 0 for the low corners, >= H
-          // for the high ones); they read the plane's first / last row, which is off the image too.
+          // x edge, position = extended row gy: z lines are columns, taps run down a tap column
           const int q = p - TH;
-          const int gy = q < 0 ? y0 + p : (q < c_lo ? -1 - q : H + c_h0 + q - c_lo);
-          slot = 2 * TW + (e - 2) * NPX + (q < 0 ? p : (q < c_lo ? TH + q : TH + R + c_h0 + q - c_lo));
           const int zc0 = e == 2 ? R : W - 1 - x0 + R;            // plane column of the edge line
-          const float* zb = zpl + zc0;
           const int zls = e == 2 ? 1 : -1;
           const float* kb = kj + (e == 2 ? R + 1 : R - 1);
           const int kls = e == 2 ? 1 : -1;
-          const int prow = gy - y0;                                // plane row of window row 0
+          if (q < 0) {
+            // a row of the tile: window rows p .. p + 6 of the plane
+            slot = 2 * TW + (e - 2) * NPX + p;
+            fold_lines<W3, KS>(zpl + p * W3 + zc0, zls, kb, kls, v0, v1, v2);
+          } else {
+            // a corner row (-1 - i or H + i): window rows outside the plane are off the image (rows < 0
+            // for the low corners, >= H for the high ones); they read the plane's first / last row,
+            // which is off the image too
+            const int gy = q < c_lo ? -1 - q : H + c_h0 + q - c_lo;
+            slot = 2 * TW + (e - 2) * NPX + (q < c_lo ? TH + q : TH + R + c_h0 + q - c_lo);
+            const int prow = gy - y0;                              // plane row of window row 0
+            float Z[R][KS], K[R][KS];
 #pragma unroll
-          for (int t = 0; t < KS; ++t) {
-            const int ro = min(max(prow + t, 0), H3 - 1) * W3;
+            for (int t = 0; t < KS; ++t) {
+              const int ro = min(max(prow + t, 0), H3 - 1) * W3;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              Z[r][t] = zb[ro + r * zls];
-              K[r][t] = kb[r * kls + t * KS];
+              for (int r = 0; r < R; ++r) {
+                Z[r][t] = zpl[zc0 + ro + r * zls];
+                K[r][t] = kb[r * kls + t * KS];
+              }
+            }
+            v0 = v1 = v2 = 0.0f;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+              v0 = fmaf(K[0][t], Z[0][t], v0);
+              v0 = fmaf(K[1][t], Z[1][t], v0);
+              v0 = fmaf(K[2][t], Z[2][t], v0);
+              v1 = fmaf(K[1][t], Z[0][t], v1);
+              v1 = fmaf(K[2][t], Z[1][t], v1);
+              v2 = fmaf(K[2][t], Z[0][t], v2);
             }
           }
-        }
-        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
-#pragma unroll
-        for (int t = 0; t < KS; ++t) {
-          v0 = fmaf(K[0][t], Z[0][t], v0);
-          v0 = fmaf(K[1][t], Z[1][t], v0);
-          v0 = fmaf(K[2][t], Z[2][t], v0);
-          v1 = fmaf(K[1][t], Z[0][t], v1);
-          v1 = fmaf(K[2][t], Z[1][t], v1);
-          v2 = fmaf(K[2][t], Z[0][t], v2);
         }
         float* fo = fpart + slot * R * NC + j;
         fo[0] += v0;
