@@ -251,6 +251,25 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
 
   double accF = 0.0, accG = 0.0, accS1 = 0.0, accS2 = 0.0, accM = 0.0;
 
+  // taps of the next chunk, fetched one chunk ahead (chunk 0: before stage 1) so that their HBM latency
+  // is hidden behind the work in between (the BF16 engine, short of registers, fetches at chunk start)
+  constexpr bool PREFETCH = FWD != FWD_MFMA_BF16;
+  constexpr int KF_PT = (KK * NC + NT - 1) / NT, KA_PT = (NC * KAP + NT - 1) / NT;
+  float kfr[KF_PT], kar[KA_PT];
+  auto fetch_taps = [&](int cn) {
+#pragma unroll
+    for (int q = 0; q < KF_PT; ++q) {
+      const int t = tid + q * NT;
+      kfr[q] = t < KK * NC ? a.kf[(size_t)cn * KK + t] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < KA_PT; ++q) {
+      const int t = tid + q * NT, j = t / KAP, tt = t - j * KAP;
+      kar[q] = t < NC * KAP && tt < KK ? a.ka[(size_t)(cn + j) * KK + tt] : 0.0f;
+    }
+  };
+  if constexpr (PREFETCH) fetch_taps(0);
+
   // ---- stage 1: step + prox on tile + 6 halo -> u6 (ADJ_HALF: u+ = e^{x+} on the tile only, x+
   // as written by FWD_HALF)
   if constexpr (UNF == ADJ_HALF) {
@@ -262,37 +281,60 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         u6[(i + 2 * R) * W6 + jx + 2 * R] = logm ? fast_exp(xn) : xn;
       }
     }
-  } else
-  for (int idx = tid; idx < H6 * W6; idx += NT) {
-    int r = idx / W6, c = idx - r * W6;
-    int gy = y0 - 2 * R + r, gx = x0 - 2 * R + c;
-    int sy = bmap(gy, H, bc), sx = bmap(gx, W, bc);
-    float uval = 0.0f;
-    if (sy >= 0 && sx >= 0) {
-      size_t p = (size_t)sy * W + sx;
-      bool own = r >= 2 * R && r < 2 * R + TH && c >= 2 * R && c < 2 * R + TW && gy < H && gx < W;
-      float fv = f[p];
-      float xn;
+  } else {
+    // the positions of this thread, two at a time: their loads first (invalid positions read pixel 0
+    // and are discarded), so that the HBM latency of the block's inputs is paid once per batch
+    constexpr int P1 = 2;
+#pragma unroll 1
+    for (int b0 = tid; b0 < H6 * W6; b0 += P1 * NT) {
+    int ps[P1];
+    bool pv[P1];
+    float fv[P1], xv[P1], xpv[P1], gv[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+      const int idx = b0 + k * NT;
+      const int r = idx / W6, c = idx - r * W6;
+      const int sy = bmap(y0 - 2 * R + r, H, bc), sx = bmap(x0 - 2 * R + c, W, bc);
+      pv[k] = idx < H6 * W6 && sy >= 0 && sx >= 0;
+      ps[k] = pv[k] ? sy * W + sx : 0;
+      fv[k] = f[ps[k]];
+      xv[k] = xc[ps[k]];
       if (a.mode == MODE_TRIAL) {
-        float xv = xc[p], xpv = xp[p], gv = gc[p];
-        float xh = xv - alpha * gv + pb.beta * (xv - xpv);
-        xn = prox_pixel(xh, fv, alpha, model, lam1, lam2, pb.newton_iters, pb.prox_method);
-        uval = logm ? fast_exp(xn) : xn;
-        if (own) {
-          xo[p] = xn;
-          float d = xn - xv, m = xv - xpv;
-          accS1 += (double)(gv * d);
-          accS2 += (double)(d * d);
-          accM += (double)(m * m);
-          accG += (double)data_term(xn, uval, fv, model, lam1, lam2);
-        }
-      } else {
-        xn = xc[p];
-        uval = logm ? fast_exp(xn) : xn;
-        if (own) accG += (double)data_term(xn, uval, fv, model, lam1, lam2);
+        xpv[k] = xp[ps[k]];
+        gv[k] = gc[ps[k]];
       }
     }
-    u6[idx] = uval;
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+      const int idx = b0 + k * NT;
+      if (idx >= H6 * W6) break;
+      const int r = idx / W6, c = idx - r * W6;
+      const int gy = y0 - 2 * R + r, gx = x0 - 2 * R + c;
+      float uval = 0.0f;
+      if (pv[k]) {
+        const bool own = r >= 2 * R && r < 2 * R + TH && c >= 2 * R && c < 2 * R + TW && gy < H && gx < W;
+        float xn;
+        if (a.mode == MODE_TRIAL) {
+          const float xh = xv[k] - alpha * gv[k] + pb.beta * (xv[k] - xpv[k]);
+          xn = prox_pixel(xh, fv[k], alpha, model, lam1, lam2, pb.newton_iters, pb.prox_method);
+          uval = logm ? fast_exp(xn) : xn;
+          if (own) {
+            xo[ps[k]] = xn;
+            const float d = xn - xv[k], m = xv[k] - xpv[k];
+            accS1 += (double)(gv[k] * d);
+            accS2 += (double)(d * d);
+            accM += (double)(m * m);
+            accG += (double)data_term(xn, uval, fv[k], model, lam1, lam2);
+          }
+        } else {
+          xn = xv[k];
+          uval = logm ? fast_exp(xn) : xn;
+          if (own) accG += (double)data_term(xn, uval, fv[k], model, lam1, lam2);
+        }
+      }
+      u6[idx] = uval;
+    }
+    }
   }
 
   // ---- fold tiles: clear the fold partials and count the fold items: positions
@@ -343,10 +385,20 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   const int nf = pb.nf;
   for (int c0 = 0; c0 < nf; c0 += NC) {
     const int ncur = min(NC, nf - c0);
-    for (int t = tid; t < KK * NC; t += NT) kf_s[t] = a.kf[(size_t)c0 * KK + t];
-    for (int t = tid; t < NC * KAP; t += NT) {
-      const int j = t / KAP, tt = t - j * KAP;
-      ka_s[t] = tt < KK ? a.ka[(size_t)(c0 + j) * KK + tt] : 0.0f;
+    if constexpr (PREFETCH) {
+#pragma unroll
+      for (int q = 0; q < KF_PT; ++q)
+        if (tid + q * NT < KK * NC) kf_s[tid + q * NT] = kfr[q];
+#pragma unroll
+      for (int q = 0; q < KA_PT; ++q)
+        if (tid + q * NT < NC * KAP) ka_s[tid + q * NT] = kar[q];
+      if (c0 + NC < nf) fetch_taps(c0 + NC);
+    } else {
+      for (int t = tid; t < KK * NC; t += NT) kf_s[t] = a.kf[(size_t)c0 * KK + t];
+      for (int t = tid; t < NC * KAP; t += NT) {
+        const int j = t / KAP, tt = t - j * KAP;
+        ka_s[t] = tt < KK ? a.ka[(size_t)(c0 + j) * KK + tt] : 0.0f;
+      }
     }
     __syncthreads();
     if constexpr (UNF == ADJ_HALF) {
