@@ -34,7 +34,7 @@ struct DevState {
   int status;              // Status
   int done;                // 1 => every later trial / decide launch is a no-op
   int input_bad;           // set by the init kernel when f or u0 is invalid
-  int pad_;
+  int pending;             // 1 => a trial has run whose partials await the decision
 };
 
 // One image of a (possibly single-image) batch: packed-plane offset, size, data-term weights and

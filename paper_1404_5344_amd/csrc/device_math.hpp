@@ -4,6 +4,53 @@
 
 namespace foe {
 
+// The backtracking decision on a trial (iPiano, as Sec. II-C adopts it) from the totals of its block
+// partials tot = {F(x+), G(x+), <grad F(x), d>, |d|^2, |x - x_prev|^2}, applied to a copy s of the
+// image's state: accept iff F(x+) <= F(x) + <grad F(x), d> + L/2 |d|^2 (descent lemma), which a
+// non-finite F(x+) or G(x+) fails; on acceptance rotate the x and gradient rings and write the stats row
+// (row: the image's stats, or null to skip the write); on rejection L <- eta_up L.  FIXED mode always
+// accepts.
+__device__ __forceinline__ void decide_step(DevState& s, const double (&tot)[5], const Problem& pb, double* row) {
+  const double F = tot[0], G = tot[1], s1 = tot[2], s2 = tot[3], m = tot[4];
+  s.trials += 1;
+  s.total_trials += 1;
+  const bool finite = isfinite(F) && isfinite(G) && isfinite(s1) && isfinite(s2);
+  if (!finite && pb.step_mode == FIXED) {
+    s.status = ST_ENONFINITE;
+    s.done = 1;
+    return;
+  }
+  const double L = s.L;
+  // a trial with a non-finite energy fails the descent test and is rejected like any other
+  const bool accept = finite && (pb.step_mode == FIXED || F <= s.Fcur + s1 + 0.5 * L * s2);
+  if (accept) {
+    if (row) {
+      row += (size_t)s.iter * STAT_COLS;
+      row[0] = F; row[1] = G; row[2] = L; row[3] = s.alpha;
+      row[4] = (double)s.trials; row[5] = s1; row[6] = s2; row[7] = m;
+    }
+    const int c = s.icur, p = s.iprev, n = s.icand;
+    s.icur = n; s.iprev = c; s.icand = p;
+    const int g = s.gcur;
+    s.gcur = s.gcand; s.gcand = g;
+    s.Fcur = F;
+    s.L_acc = L;
+    s.iter += 1;
+    s.trials = 0;
+    if (s.iter >= s.target) s.done = 1;
+    if (pb.step_mode == BACKTRACK) {
+      s.L = pb.eta_down * L;
+      s.alpha = 1.9 * (1.0 - pb.beta_d) / s.L;
+    }
+  } else if (s.trials > pb.max_backtracks) {
+    s.status = ST_ELINESEARCH;
+    s.done = 1;
+  } else {
+    s.L = pb.eta_up * L;
+    s.alpha = 1.9 * (1.0 - pb.beta_d) / s.L;
+  }
+}
+
 // One step of wave_sum_f64: v + (v moved by the DPP pattern CTRL; 0 where the pattern has no source
 // or ROW_MASK leaves the row out).
 template <int CTRL, int ROW_MASK>

@@ -55,6 +55,7 @@ struct TileCfg {
 constexpr TileCfg TILE_CFGS[2] = {{32, 32}, {32, 16}};
 constexpr int N_TILE_CFGS = 2;
 constexpr int GRAPH_BIG = 16;
+static_assert(GRAPH_BIG % 2 == 0, "a big graph must return the state to parity 0");
 
 // The paper's lambda1, lambda2 for L = 1, 3, 8 looks (Sec. III-B); other L are interpolated
 // linearly in L and L > 8 takes the L = 8 values.
@@ -96,13 +97,16 @@ struct foe_solver {
   float* kf = nullptr;
   float* ka = nullptr;
   float* theta = nullptr;
-  double* partials = nullptr;
+  double* partials = nullptr;   // per-block partials; partials2 / st2: the other parity of the graph launches
+  double* partials2 = nullptr;
   int max_tiles = 0;
   double* stats = nullptr;  // [n_img][max_iters][8]
   int stats_rows = 1;
   DevState* st = nullptr;       // [n_img]
+  DevState* st2 = nullptr;      // [n_img]
   DevState* st_host = nullptr;  // pinned mirror [n_img]
-  hipGraphExec_t graph_big = nullptr, graph_one = nullptr;
+  // GRAPH_BIG trial launches from parity 0 (back to parity 0), one launch from parity 0, one from parity 1
+  hipGraphExec_t graph_big = nullptr, graph_one = nullptr, graph_one1 = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
   int last_launches = 0;
@@ -142,6 +146,11 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
   a.g_out = g_out;
   a.st = s->st;
   a.partials = s->partials;
+  a.decide_prev = 0;
+  a.st_out = nullptr;
+  a.part_in = nullptr;
+  a.stats = s->stats;
+  a.stats_rows = s->stats_rows;
   a.kf = s->kf;
   a.ka = s->ka;
   a.theta = s->theta;
@@ -184,8 +193,9 @@ void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
     launch_cfg<32, 32>(s, a, stream);
 }
 
-void launch_decide(foe_solver* s, int mode, hipStream_t stream) {
-  decide_kernel<<<s->n_img, 256, 0, stream>>>(s->st, s->partials, s->d_images, s->pb, s->stats, s->stats_rows, mode);
+void launch_decide(foe_solver* s, int mode, hipStream_t stream, int parity = 0) {
+  decide_kernel<<<s->n_img, 256, 0, stream>>>(parity ? s->st2 : s->st, parity ? s->partials2 : s->partials, s->d_images,
+                                              s->pb, s->stats, s->stats_rows, mode);
 }
 
 dim3 grid_img(const foe_solver* s) {
@@ -274,9 +284,11 @@ void destroy_all(foe_solver* s) {
   if (!s) return;
   if (s->graph_big) (void)hipGraphExecDestroy(s->graph_big);
   if (s->graph_one) (void)hipGraphExecDestroy(s->graph_one);
+  if (s->graph_one1) (void)hipGraphExecDestroy(s->graph_one1);
   for (float* p : s->xr) if (p) (void)hipFree(p);
   for (float* p : s->gr) if (p) (void)hipFree(p);
-  void* bufs[] = {s->fbuf, s->scratch, s->zbuf, s->kf, s->ka, s->theta, s->partials, s->stats, s->st, s->d_images, s->d_tiles};
+  void* bufs[] = {s->fbuf, s->scratch, s->zbuf, s->kf, s->ka, s->theta, s->partials, s->partials2, s->stats, s->st, s->st2,
+                  s->d_images, s->d_tiles};
   for (void* b : bufs) if (b) (void)hipFree(b);
   if (s->st_host) (void)hipHostFree(s->st_host);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
@@ -288,16 +300,25 @@ void destroy_all(foe_solver* s) {
 void drop_graphs(foe_solver* s) {
   if (s->graph_big) (void)hipGraphExecDestroy(s->graph_big);
   if (s->graph_one) (void)hipGraphExecDestroy(s->graph_one);
-  s->graph_big = s->graph_one = nullptr;
+  if (s->graph_one1) (void)hipGraphExecDestroy(s->graph_one1);
+  s->graph_big = s->graph_one = s->graph_one1 = nullptr;
 }
 
-foe_status build_graph(foe_solver* s, int slots, hipGraphExec_t* out) {
+// A graph of `slots` trial launches starting at `parity`: launch n reads the state and the partials of
+// parity (parity + n) % 2, decides the previous trial in every workgroup, runs its own trial and writes
+// the state and the partials of the other parity.  No separate decision launch between trials.
+foe_status build_graph(foe_solver* s, int slots, int parity, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIP_OR(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-  FusedArgs a = fused_args(s, MODE_TRIAL, s->fbuf, nullptr, nullptr);
   for (int k = 0; k < slots; ++k) {
+    const int q = (parity + k) & 1;
+    FusedArgs a = fused_args(s, MODE_TRIAL, s->fbuf, nullptr, nullptr);
+    a.decide_prev = 1;
+    a.st = q ? s->st2 : s->st;
+    a.st_out = q ? s->st : s->st2;
+    a.part_in = q ? s->partials2 : s->partials;
+    a.partials = q ? s->partials : s->partials2;
     launch_fused(s, a, s->cap_stream);
-    launch_decide(s, DECIDE_STEP, s->cap_stream);
   }
   HIP_OR(hipStreamEndCapture(s->cap_stream, &g));
   hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -358,9 +379,11 @@ foe_status run_loop(foe_solver* s, const double* L_in, int iters, foe_summary* s
   launch_decide(s, DECIDE_INIT, s->stream);
   HIP_OR(hipGetLastError());
   if (!s->graph_big) {
-    e = build_graph(s, GRAPH_BIG, &s->graph_big);
+    e = build_graph(s, GRAPH_BIG, 0, &s->graph_big);
     if (e != FOE_OK) return e;
-    e = build_graph(s, 1, &s->graph_one);
+    e = build_graph(s, 1, 0, &s->graph_one);
+    if (e != FOE_OK) return e;
+    e = build_graph(s, 1, 1, &s->graph_one1);
     if (e != FOE_OK) return e;
   }
   HIP_OR(hipEventRecord(s->ev0, s->stream));
@@ -376,8 +399,16 @@ foe_status run_loop(foe_solver* s, const double* L_in, int iters, foe_summary* s
       if (!h.done) remaining = std::max(remaining, h.target - h.iter);
     }
     if (remaining <= 0) break;
+    // the state and partials start at parity 0; GRAPH_BIG is even, so each big graph ends at parity 0
+    int q = 0;
     for (int k = 0; k < remaining / GRAPH_BIG; ++k) HIP_OR(hipGraphLaunch(s->graph_big, s->stream));
-    for (int k = 0; k < remaining % GRAPH_BIG; ++k) HIP_OR(hipGraphLaunch(s->graph_one, s->stream));
+    for (int k = 0; k < remaining % GRAPH_BIG; ++k) {
+      HIP_OR(hipGraphLaunch(q ? s->graph_one1 : s->graph_one, s->stream));
+      q ^= 1;
+    }
+    // the decision on the last trial, then the state back to parity 0
+    launch_decide(s, DECIDE_STEP, s->stream, q);
+    if (q) HIP_OR(hipMemcpyAsync(s->st, s->st2, sizeof(DevState) * s->n_img, hipMemcpyDeviceToDevice, s->stream));
     launches += remaining;
     e = pull_states(s);
     if (e != FOE_OK) return e;
@@ -460,8 +491,9 @@ foe_status create_common(const foe_params* p, int n_img, const int32_t* H, const
   ok = ok && alloc((void**)&s->kf, sizeof(float) * MAX_NF * KK) && alloc((void**)&s->ka, sizeof(float) * MAX_NF * KK);
   ok = ok && alloc((void**)&s->theta, sizeof(float) * MAX_NF);
   ok = ok && alloc((void**)&s->partials, sizeof(double) * PART_COLS * (size_t)s->max_tiles);
+  ok = ok && alloc((void**)&s->partials2, sizeof(double) * PART_COLS * (size_t)s->max_tiles);
   ok = ok && alloc((void**)&s->stats, sizeof(double) * STAT_COLS * (size_t)s->stats_rows * n_img);
-  ok = ok && alloc((void**)&s->st, sizeof(DevState) * n_img);
+  ok = ok && alloc((void**)&s->st, sizeof(DevState) * n_img) && alloc((void**)&s->st2, sizeof(DevState) * n_img);
   ok = ok && alloc((void**)&s->d_images, sizeof(ImageDesc) * n_img);
   ok = ok && alloc((void**)&s->d_tiles, sizeof(TileDesc) * (size_t)s->max_tiles);
   ok = ok && hipHostMalloc((void**)&s->st_host, sizeof(DevState) * n_img, hipHostMallocDefault) == hipSuccess;

@@ -40,14 +40,10 @@ __global__ void check_input_kernel(const float* __restrict__ f, const ImageDesc*
 
 enum DecideMode { DECIDE_STEP = 0, DECIDE_INIT = 1, DECIDE_REPORT = 2 };
 
-// Single-block reduction of the per-block partials in a fixed order, then (DECIDE_STEP) the
-// backtracking test: accept iff F(x+) <= F(x) + <grad F(x), d> + L/2 |d|^2 (descent lemma), which a
-// non-finite F(x+) or G(x+) fails;
-// on acceptance rotate the x and gradient rings and record the stats row; on rejection
-// L <- eta_up L.  FIXED mode always accepts.
-// One block per image: block b reduces the partials of image b's tiles.
-// The decision for one image, run by the first 256 threads of a block (every thread of the block
-// calls it: it contains a barrier).  The sums take the same fixed order wherever it runs.
+// Single-block reduction of the per-block partials in a fixed order, then by mode: REPORT stores the totals;
+// INIT also takes F(x^0) and checks the inputs; STEP settles a trial that has run and awaits its decision
+// (decide_step).  One block per image reduces the partials of that image's tiles; the first 256 threads take
+// part (every thread of the block calls it: it contains a barrier).
 __device__ __forceinline__ void decide_block(DevState* st, const double* __restrict__ partials, const ImageDesc& im,
                                              const Problem& pb, double* stats, int mode) {
   __shared__ double red[256 / 64][5];
@@ -66,56 +62,26 @@ __device__ __forceinline__ void decide_block(DevState* st, const double* __restr
   if (threadIdx.x != 0) return;
   double tot[5];
   for (int k = 0; k < 5; ++k) tot[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
-  for (int k = 0; k < 5; ++k) st->sums[k] = tot[k];
-  if (mode == DECIDE_REPORT) return;
+  DevState s = *st;
+  if (mode == DECIDE_STEP) {
+    if (!s.pending) return;   // nothing ran since the last decision
+    s.pending = 0;
+  }
+  for (int k = 0; k < 5; ++k) s.sums[k] = tot[k];
   if (mode == DECIDE_INIT) {
-    st->Fcur = tot[0];
-    if (st->input_bad) {
-      st->status = ST_EINPUT;
-      st->done = 1;
+    s.Fcur = tot[0];
+    if (s.input_bad) {
+      s.status = ST_EINPUT;
+      s.done = 1;
     } else if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-      st->status = ST_ENONFINITE;
-      st->done = 1;
+      s.status = ST_ENONFINITE;
+      s.done = 1;
     }
-    if (st->target <= 0) st->done = 1;
-    return;
+    if (s.target <= 0) s.done = 1;
+  } else if (mode == DECIDE_STEP) {
+    decide_step(s, tot, pb, stats);
   }
-  const double F = tot[0], G = tot[1], s1 = tot[2], s2 = tot[3], m = tot[4];
-  st->trials += 1;
-  st->total_trials += 1;
-  const bool finite = isfinite(F) && isfinite(G) && isfinite(s1) && isfinite(s2);
-  if (!finite && pb.step_mode == FIXED) {
-    st->status = ST_ENONFINITE;
-    st->done = 1;
-    return;
-  }
-  const double L = st->L;
-  // a trial with a non-finite energy fails the descent test and is rejected like any other
-  const bool accept = finite && (pb.step_mode == FIXED || F <= st->Fcur + s1 + 0.5 * L * s2);
-  if (accept) {
-    double* row = stats + (size_t)st->iter * STAT_COLS;
-    row[0] = F; row[1] = G; row[2] = L; row[3] = st->alpha;
-    row[4] = (double)st->trials; row[5] = s1; row[6] = s2; row[7] = m;
-    const int c = st->icur, p = st->iprev, n = st->icand;
-    st->icur = n; st->iprev = c; st->icand = p;
-    const int g = st->gcur;
-    st->gcur = st->gcand; st->gcand = g;
-    st->Fcur = F;
-    st->L_acc = L;
-    st->iter += 1;
-    st->trials = 0;
-    if (st->iter >= st->target) st->done = 1;
-    if (pb.step_mode == BACKTRACK) {
-      st->L = pb.eta_down * L;
-      st->alpha = 1.9 * (1.0 - pb.beta_d) / st->L;
-    }
-  } else if (st->trials > pb.max_backtracks) {
-    st->status = ST_ELINESEARCH;
-    st->done = 1;
-  } else {
-    st->L = pb.eta_up * L;
-    st->alpha = 1.9 * (1.0 - pb.beta_d) / st->L;
-  }
+  *st = s;
 }
 
 // One block per image: block b reduces the partials of image b's tiles and decides.

@@ -39,8 +39,16 @@ struct FusedArgs {
   float* gr0; float* gr1;               // gradient ring (TRIAL), packed
   const float* x_in;                    // EVAL input, packed
   float* g_out;                         // EVAL output, packed
-  DevState* st;                         // per-image states
-  double* partials;                     // [gridDim.x][PART_COLS]
+  DevState* st;                         // per-image states (read)
+  double* partials;                     // [gridDim.x][PART_COLS] (written)
+  // decide_prev: before its own trial every workgroup reduces part_in (the previous trial's partials) over
+  // its image's tiles and applies the line-search decision to a copy of st; the image's first workgroup
+  // stores the decided state (pending = 1 unless done) to st_out and the accepted stats row.
+  int decide_prev;
+  DevState* st_out;
+  const double* part_in;
+  double* stats;                        // [images][stats_rows][STAT_COLS]
+  int stats_rows;
   const float* kf;                      // forward taps, flipped and chunk-transposed:
                                         //   kf[(c * KK + a * 7 + b) * NC + j] = k_{c*NC+j}[6-a][6-b]
   const float* ka;                      // adjoint taps: ka[i][a][b] = 2 theta_i k_i[a][b]
@@ -225,32 +233,6 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   const bool logm = model != IDIV;
   const int x0 = td.x0, y0 = td.y0;
 
-  const float* xc;
-  const float* xp = nullptr;
-  const float* gc = nullptr;
-  float* xo = nullptr;
-  float* go;
-  float alpha = 0.0f;
-  if (a.mode == MODE_TRIAL) {
-    const DevState* st = a.st + td.image;
-    if (st->done) return;
-    alpha = (float)st->alpha;
-    xc = pick3(st->icur, a.xr0, a.xr1, a.xr2) + im.off;
-    xp = pick3(st->iprev, a.xr0, a.xr1, a.xr2) + im.off;
-    xo = pick3(st->icand, a.xr0, a.xr1, a.xr2) + im.off;
-    gc = pick2(st->gcur, a.gr0, a.gr1) + im.off;
-    go = pick2(st->gcand, a.gr0, a.gr1) + im.off;
-  } else {
-    xc = a.x_in + im.off;
-    go = a.g_out + im.off;
-  }
-  const float* __restrict__ f = a.f + im.off;
-  const bool fold = UNF != FWD_HALF && bc == SYMMETRIC && (y0 < R || y0 + TH > H - R || x0 < R || x0 + TW > W - R);
-  // every R3 position (tile + 3) in the image: z needs no mask, every tile position is an own one
-  const bool all_in = y0 >= R && y0 + TH + R <= H && x0 >= R && x0 + TW + R <= W;
-
-  double accF = 0.0, accG = 0.0, accS1 = 0.0, accS2 = 0.0, accM = 0.0;
-
   // taps of the next chunk, fetched one chunk ahead (chunk 0: before stage 1) so that their HBM latency
   // is hidden behind the work in between (the BF16 engine, short of registers, fetches at chunk start)
   constexpr bool PREFETCH = FWD != FWD_MFMA_BF16;
@@ -269,6 +251,70 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     }
   };
   if constexpr (PREFETCH) fetch_taps(0);
+
+  const float* xc;
+  const float* xp = nullptr;
+  const float* gc = nullptr;
+  float* xo = nullptr;
+  float* go;
+  float alpha = 0.0f;
+  if (a.mode == MODE_TRIAL) {
+    const DevState* st = a.st + td.image;
+    __shared__ DevState s_dec;
+    if (a.decide_prev) {
+      // the decision on the previous trial of this image: every workgroup of the image reduces the same
+      // partials in the same fixed order and so takes the same decision (no inter-workgroup sync).  The
+      // state is fetched together with the partials.
+      if (tid == 0) s_dec = *st;
+      double v[5] = {0, 0, 0, 0, 0};
+      for (int b = im.tile0 + tid; b < im.tile0 + im.ntiles; b += NT)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) v[k] += a.part_in[(size_t)b * PART_COLS + k];
+      const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) v[k] = wave_sum_f64(v[k]);
+      if (lane == 63)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) red[wave * 5 + k] = v[k];
+      __syncthreads();
+      if (tid == 0) {
+        double tot[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          double t = 0.0;
+          for (int w = 0; w < NT / 64; ++w) t += red[w * 5 + k];
+          tot[k] = t;
+        }
+        const bool writer = (int)blockIdx.x == im.tile0;
+        if (s_dec.pending && !s_dec.done) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) s_dec.sums[k] = tot[k];
+          decide_step(s_dec, tot, pb, writer ? a.stats + (size_t)td.image * a.stats_rows * STAT_COLS : nullptr);
+        }
+        s_dec.pending = s_dec.done ? 0 : 1;   // this launch runs the next trial unless the image is done
+        if (writer) a.st_out[td.image] = s_dec;
+      }
+      __syncthreads();
+      st = &s_dec;
+    }
+    if (st->done) return;
+    alpha = (float)st->alpha;
+    xc = pick3(st->icur, a.xr0, a.xr1, a.xr2) + im.off;
+    xp = pick3(st->iprev, a.xr0, a.xr1, a.xr2) + im.off;
+    xo = pick3(st->icand, a.xr0, a.xr1, a.xr2) + im.off;
+    gc = pick2(st->gcur, a.gr0, a.gr1) + im.off;
+    go = pick2(st->gcand, a.gr0, a.gr1) + im.off;
+  } else {
+    xc = a.x_in + im.off;
+    go = a.g_out + im.off;
+  }
+  const float* __restrict__ f = a.f + im.off;
+  const bool fold = UNF != FWD_HALF && bc == SYMMETRIC && (y0 < R || y0 + TH > H - R || x0 < R || x0 + TW > W - R);
+  // every R3 position (tile + 3) in the image: z needs no mask, every tile position is an own one
+  const bool all_in = y0 >= R && y0 + TH + R <= H && x0 >= R && x0 + TW + R <= W;
+
+  double accF = 0.0, accG = 0.0, accS1 = 0.0, accS2 = 0.0, accM = 0.0;
+
 
   // ---- stage 1: step + prox on tile + 6 halo -> u6 (ADJ_HALF: u+ = e^{x+} on the tile only, x+
   // as written by FWD_HALF)
