@@ -49,6 +49,8 @@ foe_status fail(foe_status st, const std::string& msg) {
 // V_NT threads per workgroup; the FP32 matrix-core engine runs V_NT_MFMA (16 waves: four per SIMD hide
 // the LDS and matrix-pipe latencies better, and its registers fit in the 128 VGPRs that allows).
 constexpr int V_NC = 16, V_NT = 512, V_NT_MFMA = 1024, V_BR = 4, V_BC = 2;
+// adjoint block width of the FP32 matrix-core kernels: 4 x 4 output blocks on 32 x 32 tiles
+constexpr int bc_mfma(int th) { return th == 32 ? 4 : V_BC; }
 struct TileCfg {
   int tw, th;
 };
@@ -165,7 +167,7 @@ void launch_engine(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
   if (s->pb.engine == FWD_MFMA_BF16)
     foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
   else if (s->pb.engine == FWD_MFMA_F32)
-    foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, V_BC, FWD_MFMA_F32, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
+    foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_F32, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
   else
     foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
 }
@@ -178,7 +180,7 @@ void launch_cfg(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
     // the adjoint half runs no forward bank; it takes the thread count of the engine's fused kernel,
     // so that both paths sum the adjoint over the filter groups in the same order
     if (s->pb.engine == FWD_MFMA_F32)
-      foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, V_BC, FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
+      foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
     else
       foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT, 0, stream>>>(a);
   } else {
