@@ -33,7 +33,7 @@ METRIC = "Mpixel-iters/s iPiano-FoE on 1 GPU; time-to-PSNR vs plain FP32; roofli
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 peak, vector and matrix cores alike
 NF, KK = 48, 49
 FLOP_PER_PX_TRIAL = 2 * 2 * NF * KK   # forward bank on x+ and adjoint bank, one FMA = 2 flop
-KERNEL_SOURCES = ["common.hpp", "device_math.hpp", "kernels_trial.hpp"]
+KERNEL_SOURCES = ["common.hpp", "device_math.hpp", "kernels_trial.hpp", "foe_lib.hip"]   # kernels and their launch shapes
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "foe_trial_kernel_512x512_hbm_traffic.md")
 
 
