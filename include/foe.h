@@ -61,7 +61,12 @@ typedef enum foe_model { FOE_MODEL_COMBINED = 0, FOE_MODEL_LOG = 1, FOE_MODEL_ID
 typedef enum foe_boundary { FOE_BC_SYMMETRIC = 0, FOE_BC_ZERO = 1, FOE_BC_PERIODIC = 2 } foe_boundary;
 typedef enum foe_step_mode { FOE_STEP_BACKTRACK = 0, FOE_STEP_FIXED = 1 } foe_step_mode;
 typedef enum foe_precision { FOE_PREC_FP32 = 0, FOE_PREC_BF16 = 1 } foe_precision;
-typedef enum foe_engine { FOE_ENGINE_AUTO = 0, FOE_ENGINE_VALU = 1, FOE_ENGINE_MFMA = 2 } foe_engine;
+typedef enum foe_engine {
+  FOE_ENGINE_AUTO = 0,
+  FOE_ENGINE_VALU = 1,
+  FOE_ENGINE_MFMA = 2,
+  FOE_ENGINE_MFMA_SPLIT = 3
+} foe_engine;
 typedef enum foe_fusion { FOE_FUSED = 0, FOE_UNFUSED = 1 } foe_fusion;
 typedef enum foe_prox { FOE_PROX_NEWTON = 0, FOE_PROX_LAMBERTW = 1 } foe_prox;
 
@@ -79,7 +84,14 @@ typedef struct foe_params {
   int32_t max_backtracks;  /* rejected trials allowed per iteration, >= 0 */
   int32_t newton_iters;    /* log-model prox: at most this many Newton iterations per pixel (each
                               pixel stops when converged), 1 .. 100 */
-  int32_t engine;          /* foe_engine: VALU direct convolution or MFMA implicit GEMM */
+  int32_t engine;          /* foe_engine, for FP32 precision: VALU = direct convolution; MFMA = implicit
+                              GEMM on FP32 matrix cores (v_mfma_f32_16x16x4f32); MFMA_SPLIT = the same
+                              GEMM on FP16 matrix cores (v_mfma_f32_16x16x32_f16), each FP32 operand
+                              split into an FP16 head and a scaled FP16 tail (about 22 significant bits,
+                              exact products, FP32 accumulation; u scaled per tile by a power of two;
+                              every |tap| < 16384, else EINVAL); AUTO = MFMA_SPLIT when the taps allow
+                              it, else MFMA.  BF16 precision always runs its own MFMA kernel (AUTO or
+                              MFMA, else EINVAL). */
   int32_t fusion;          /* foe_fusion: FUSED keeps the 48 z planes on chip; UNFUSED writes them to
                               HBM between a forward and an adjoint launch (num_filters * pixels
                               extra floats of device memory; same results up to summation order) */

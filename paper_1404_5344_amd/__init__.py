@@ -21,7 +21,7 @@ COMBINED, LOG, IDIV = 0, 1, 2
 SYMMETRIC, ZERO, PERIODIC = 0, 1, 2
 BACKTRACK, FIXED = 0, 1
 FP32, BF16 = 0, 1
-ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA = 0, 1, 2
+ENGINE_AUTO, ENGINE_VALU, ENGINE_MFMA, ENGINE_MFMA_SPLIT = 0, 1, 2, 3
 STATS_COLS = 8
 STATS_NAMES = ("F", "G", "L", "alpha", "trials", "s1", "s2", "m")
 

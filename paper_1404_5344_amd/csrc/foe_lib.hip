@@ -73,6 +73,37 @@ void paper_lambdas(int looks, double* l1, double* l2) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Largest |tap| the split-FP16 engine takes: the heads stay below 2^14 and the 4096-scaled tails
+// below 2^15, inside the FP16 range.
+constexpr float SPLIT_MAX_TAP = 16384.0f;
+
+// The split-FP16 operands of the forward taps kf ([chunk][t][j], t = 7 a + b): per chunk and lane
+// (m = lane % 16, k = lane / 16), for steps s = 0, 1, the heads then the 4096-scaled tails of tap
+// row 4s + k, columns 0..7, of filter m (zero outside the 7 x 7 taps), two FP16 per word, the lower
+// column in the low half.
+std::vector<unsigned> split_taps(const std::vector<float>& kf) {
+  const int nchunks = MAX_NF / V_NC;
+  std::vector<unsigned> out((size_t)nchunks * F16_OPS, 0u);
+  for (int c = 0; c < nchunks; ++c)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int m = lane % 16, k = lane / 16;
+      for (int s = 0; s < 2; ++s)
+        for (int part = 0; part < 2; ++part)
+          for (int i = 0; i < 8; i += 2) {
+            unsigned short hv[2];
+            for (int q = 0; q < 2; ++q) {
+              const int ta = 4 * s + k, tb = i + q;
+              const float v = ta < KS && tb < KS ? kf[((size_t)c * KK + ta * KS + tb) * V_NC + m] : 0.0f;
+              const _Float16 hi = (_Float16)v;
+              const _Float16 h = part == 0 ? hi : (_Float16)((v - (float)hi) * 4096.0f);
+              hv[q] = __builtin_bit_cast(unsigned short, h);
+            }
+            out[(size_t)c * F16_OPS + lane * 16 + s * 8 + part * 4 + i / 2] = (unsigned)hv[0] | ((unsigned)hv[1] << 16);
+          }
+    }
+  return out;
+}
+
 }  // namespace
 
 // Lets the other translation units of the library report through foe_last_error().
@@ -98,6 +129,7 @@ struct foe_solver {
   float* zbuf = nullptr;     // unfused path: num_filters packed planes of z
   float* kf = nullptr;
   float* ka = nullptr;
+  unsigned* kf16 = nullptr;  // split-FP16 forward operands (FP16 pairs), F16_OPS words per chunk
   float* theta = nullptr;
   double* partials = nullptr;   // per-block partials; partials2 / st2: the other parity of the graph launches
   double* partials2 = nullptr;
@@ -155,6 +187,7 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
   a.stats_rows = s->stats_rows;
   a.kf = s->kf;
   a.ka = s->ka;
+  a.kf16 = s->kf16;
   a.theta = s->theta;
   a.zbuf = s->zbuf;
   a.zstride = (long long)s->n;
@@ -168,6 +201,8 @@ void launch_engine(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
     foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
   else if (s->pb.engine == FWD_MFMA_F32)
     foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_F32, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
+  else if (s->pb.engine == FWD_MFMA_F16X)
+    foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_F16X, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
   else
     foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
 }
@@ -179,7 +214,7 @@ void launch_cfg(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
     launch_engine<TW, TH, FWD_HALF>(s, a, stream);
     // the adjoint half runs no forward bank; it takes the thread count of the engine's fused kernel,
     // so that both paths sum the adjoint over the filter groups in the same order
-    if (s->pb.engine == FWD_MFMA_F32)
+    if (s->pb.engine == FWD_MFMA_F32 || s->pb.engine == FWD_MFMA_F16X)
       foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
     else
       foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT, 0, stream>>>(a);
@@ -221,12 +256,12 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   if (p->model < 0 || p->model > 2) return fail(FOE_EINVAL, "bad model");
   if (p->boundary < 0 || p->boundary > 2) return fail(FOE_EINVAL, "bad boundary");
   if (p->precision != FOE_PREC_FP32 && p->precision != FOE_PREC_BF16) return fail(FOE_EINVAL, "bad precision");
-  if (p->engine < FOE_ENGINE_AUTO || p->engine > FOE_ENGINE_MFMA) return fail(FOE_EINVAL, "bad engine");
+  if (p->engine < FOE_ENGINE_AUTO || p->engine > FOE_ENGINE_MFMA_SPLIT) return fail(FOE_EINVAL, "bad engine");
   if (p->fusion != FOE_FUSED && p->fusion != FOE_UNFUSED) return fail(FOE_EINVAL, "bad fusion");
   if (p->prox_method != FOE_PROX_NEWTON && p->prox_method != FOE_PROX_LAMBERTW) return fail(FOE_EINVAL, "bad prox_method");
   if (p->prox_method == FOE_PROX_LAMBERTW && p->model != FOE_MODEL_LOG)
     return fail(FOE_EINVAL, "the Lambert-W prox exists for the LOG model only");
-  if (p->precision == FOE_PREC_BF16 && p->engine == FOE_ENGINE_VALU)
+  if (p->precision == FOE_PREC_BF16 && (p->engine == FOE_ENGINE_VALU || p->engine == FOE_ENGINE_MFMA_SPLIT))
     return fail(FOE_EINVAL, "BF16 precision runs on the MFMA engine");
   if (p->step_mode != FOE_STEP_BACKTRACK && p->step_mode != FOE_STEP_FIXED) return fail(FOE_EINVAL, "bad step_mode");
   if (p->max_iters < 0) return fail(FOE_EINVAL, "max_iters must be >= 0");
@@ -239,8 +274,13 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
     if (!(std::isfinite(p->eta_up) && p->eta_up > 1.0)) return fail(FOE_EINVAL, "eta_up must be > 1");
     if (!(p->eta_down > 0.0 && p->eta_down <= 1.0)) return fail(FOE_EINVAL, "eta_down must be in (0, 1]");
   }
-  for (int i = 0; i < p->num_filters * FOE_KSIZE * FOE_KSIZE; ++i)
+  bool split_ok = true;
+  for (int i = 0; i < p->num_filters * FOE_KSIZE * FOE_KSIZE; ++i) {
     if (!std::isfinite(filters[i])) return fail(FOE_EINVAL, "non-finite filter tap");
+    if (!(std::fabs(filters[i]) < SPLIT_MAX_TAP)) split_ok = false;
+  }
+  if (p->engine == FOE_ENGINE_MFMA_SPLIT && !split_ok)
+    return fail(FOE_EINVAL, "the split-FP16 engine takes taps with |k| < 16384");
   for (int i = 0; i < p->num_filters; ++i)
     if (!(std::isfinite(weights[i]) && weights[i] >= 0.0f)) return fail(FOE_EINVAL, "weights must be finite, >= 0");
   pb->nf = p->num_filters;
@@ -255,8 +295,14 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   pb->eta_up = p->eta_up;
   pb->eta_down = p->eta_down;
   pb->alpha_fixed = p->alpha_fixed;
-  pb->engine = p->precision == FOE_PREC_BF16 ? FWD_MFMA_BF16
-               : (p->engine == FOE_ENGINE_VALU ? FWD_VALU : FWD_MFMA_F32);
+  if (p->precision == FOE_PREC_BF16)
+    pb->engine = FWD_MFMA_BF16;
+  else if (p->engine == FOE_ENGINE_VALU)
+    pb->engine = FWD_VALU;
+  else if (p->engine == FOE_ENGINE_MFMA)
+    pb->engine = FWD_MFMA_F32;
+  else   // MFMA_SPLIT, or AUTO: the split engine unless a tap is out of its range
+    pb->engine = split_ok ? FWD_MFMA_F16X : FWD_MFMA_F32;
   return FOE_OK;
 }
 
@@ -289,7 +335,7 @@ void destroy_all(foe_solver* s) {
   if (s->graph_one1) (void)hipGraphExecDestroy(s->graph_one1);
   for (float* p : s->xr) if (p) (void)hipFree(p);
   for (float* p : s->gr) if (p) (void)hipFree(p);
-  void* bufs[] = {s->fbuf, s->scratch, s->zbuf, s->kf, s->ka, s->theta, s->partials, s->partials2, s->stats, s->st, s->st2,
+  void* bufs[] = {s->fbuf, s->scratch, s->zbuf, s->kf, s->ka, s->kf16, s->theta, s->partials, s->partials2, s->stats, s->st, s->st2,
                   s->d_images, s->d_tiles};
   for (void* b : bufs) if (b) (void)hipFree(b);
   if (s->st_host) (void)hipHostFree(s->st_host);
@@ -491,6 +537,7 @@ foe_status create_common(const foe_params* p, int n_img, const int32_t* H, const
   ok = ok && alloc((void**)&s->fbuf, plane) && alloc((void**)&s->scratch, plane);
   if (p->fusion == FOE_UNFUSED) ok = ok && alloc((void**)&s->zbuf, plane * p->num_filters);
   ok = ok && alloc((void**)&s->kf, sizeof(float) * MAX_NF * KK) && alloc((void**)&s->ka, sizeof(float) * MAX_NF * KK);
+  ok = ok && alloc((void**)&s->kf16, sizeof(unsigned) * (MAX_NF / V_NC) * F16_OPS);
   ok = ok && alloc((void**)&s->theta, sizeof(float) * MAX_NF);
   ok = ok && alloc((void**)&s->partials, sizeof(double) * PART_COLS * (size_t)s->max_tiles);
   ok = ok && alloc((void**)&s->partials2, sizeof(double) * PART_COLS * (size_t)s->max_tiles);
@@ -514,7 +561,9 @@ foe_status create_common(const foe_params* p, int n_img, const int32_t* H, const
         kf[((size_t)c * KK + t) * V_NC + j] = k;
       }
   }
+  const std::vector<unsigned> kf16 = split_taps(kf);
   hipError_t e = hipMemcpy(s->kf, kf.data(), sizeof(float) * kf.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->kf16, kf16.data(), sizeof(unsigned) * kf16.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->ka, ka.data(), sizeof(float) * ka.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->theta, th.data(), sizeof(float) * th.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreate(&s->ev0);

@@ -21,7 +21,7 @@
 namespace foe {
 
 enum FusedMode { MODE_TRIAL = 0, MODE_EVAL = 1 };
-enum ForwardEngine { FWD_VALU = 0, FWD_MFMA_F32 = 1, FWD_MFMA_BF16 = 2 };
+enum ForwardEngine { FWD_VALU = 0, FWD_MFMA_F32 = 1, FWD_MFMA_BF16 = 2, FWD_MFMA_F16X = 3 };
 // Fusion of the gradient: the whole trial in one kernel (FUSED), or split in two launches that
 // exchange the 48 z planes through HBM: FWD_HALF runs stages 1-2 (step, prox, forward bank,
 // energies) and stores z_i on the tile, ADJ_HALF loads z_i on the tile + 3 halo and runs stage 3
@@ -29,6 +29,8 @@ enum ForwardEngine { FWD_VALU = 0, FWD_MFMA_F32 = 1, FWD_MFMA_BF16 = 2 };
 enum Fusion { FUSED = 0, FWD_HALF = 1, ADJ_HALF = 2 };
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct FusedArgs {
   Problem pb;
@@ -52,6 +54,8 @@ struct FusedArgs {
   const float* kf;                      // forward taps, flipped and chunk-transposed:
                                         //   kf[(c * KK + a * 7 + b) * NC + j] = k_{c*NC+j}[6-a][6-b]
   const float* ka;                      // adjoint taps: ka[i][a][b] = 2 theta_i k_i[a][b]
+  const unsigned* kf16;                 // split-FP16 forward operands: per chunk, F16_OPS words in the
+                                        //   lane order of the split engine (ForwardOps<FWD_MFMA_F16X>)
   const float* theta;
   float* zbuf;                          // unfused z planes: zbuf[i * zstride + off + y * W + x]
   long long zstride;
@@ -102,6 +106,44 @@ __device__ __forceinline__ void fold_lines(const float* zb, int zls, const float
   }
 }
 
+// Operands of the matrix-core forward bank that stay in registers for one chunk of 16 filters.
+//   FP32 engine: taps 0..47 in twelve steps of v_mfma_f32_16x16x4f32 (lane (m, k): A = filter m at
+//   tap 4s + k, B = u6 at that tap of position m); the VALU adds tap 48.
+//   Split-FP16 engine: the 7 x 7 taps laid out as 8 x 8 (tap row, tap column; row 7 and column 7
+//   zero) in two steps of v_mfma_f32_16x16x32_f16: in step s lane (m, k) holds tap row 4s + k,
+//   columns 0..7, of filter m (A) and of position m (B).  Every FP32 operand v is split into two FP16
+//   numbers, v = hi + lo / 4096 with hi = fp16(v), lo = fp16(4096 (v - hi)), which keeps about 22
+//   significant bits of v; y = hi.hi + (lo.hi + hi.lo) / 4096, where every product of two FP16
+//   numbers is exact in FP32 and only the lo.lo term (2^-22 of the product) is dropped.  u is split
+//   after scaling by the tile's power of two 2^-E (largest |u| of the tile in [2^13, 2^14)), so that
+//   no u of any range overflows FP16; y is scaled back by 2^E.
+constexpr int F16_OPS = 64 * 16;   // words of split-FP16 tap operands per chunk: 16 per lane
+template <int FWD> struct ForwardOps;
+template <> struct ForwardOps<FWD_MFMA_F32> {
+  float a[KK / 4];
+  int toff[KK / 4];
+  float4 klast;
+};
+template <> struct ForwardOps<FWD_MFMA_F16X> {
+  half8 hi[2], lo[2];   // A operands of the two steps (FP16 heads, 4096-scaled tails)
+  float sc, sclo;       // 2^E and 2^(E - 12)
+};
+
+// LDS planes of the split-FP16 engine: u6 / 2^E as FP16 heads and tails, row by row ([head row][tail
+// row], COLS halves each), in two copies: copy 0 holds column c at c, copy 1 holds column c + 1 at c,
+// so that the 8 consecutive columns of a B operand start on a 4-byte boundary in one of them.  One
+// padding row and the padding columns hold zeros: they meet the zero taps of row 7 and column 7.
+template <int TW, int TH>
+struct SplitPlanes {
+  static constexpr int W6 = TW + 4 * R, H6 = TH + 4 * R;
+  static constexpr int COLS = W6 + 2;            // halves per head / tail row (even)
+  static constexpr int ROWS = H6 + 1;
+  static constexpr int ROW_W = COLS;             // words per plane row (head + tail)
+  static constexpr int COPY_W = ROWS * ROW_W;    // words per copy
+  static constexpr int WORDS = 2 * COPY_W;
+  static constexpr int TAIL_W = COLS / 2;        // word offset of the tail row
+};
+
 // One chunk of the FP32 matrix-core forward bank on the R3 region of a TW x TH tile: the position
 // groups g0, g0 + GS, ... (16 consecutive positions each, GS groups apart).  Per group, twelve
 // v_mfma_f32_16x16x4f32 take taps 0..47 (lane (m, k): A = filter m at tap 4s + k, B = u6 at tap
@@ -112,10 +154,12 @@ __device__ __forceinline__ void fold_lines(const float* zb, int zls, const float
 // the own positions to HBM (zb = plane of the chunk's first filter at the image, zstride apart).
 // Lanes past the last position compute position 0 and store its value there again: the same bits
 // as the lane that owns it, so the duplicate store is harmless.
-template <int TW, int TH, int NC, int GS, int FUSION, bool ALL_IN>
-__device__ __forceinline__ float mfma_forward_chunk(const float* u6, float* zp, const float (&a_reg)[KK / 4],
-                                                    const int (&toff)[KK / 4], float4 klast, const float (&thl)[4], int g0, int lm, int lk, int y0, int x0,
-                                                    int H, int W, bool periodic, float* zb, long long zstride, int nlive) {
+template <int TW, int TH, int NC, int GS, int FUSION, bool ALL_IN, int FWD>
+__device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsigned* u16, float* zp,
+                                                    const ForwardOps<FWD>& ops, const float (&thl)[4], int g0, int lm,
+                                                    int lk, int y0, int x0, int H, int W, bool periodic, float* zb,
+                                                    long long zstride, int nlive) {
+  using SP = SplitPlanes<TW, TH>;
   constexpr int W6 = TW + 4 * R, W3 = TW + 2 * R, H3 = TH + 2 * R, PLANE = H3 * W3;
   constexpr int NGROUP = (PLANE + 15) / 16;
   constexpr int STEP = GS * 16, DR = STEP / W3, DC = STEP % W3;   // position advance per pass
@@ -128,15 +172,34 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, float* zp, 
     constexpr bool PARTIAL = decltype(partial_tag)::value;
     const bool inr = !PARTIAL || p < PLANE;
     const int rr = inr ? r : 0, cc = inr ? c : 0, zo = inr ? p : 0;
-    const int pbase = rr * W6 + cc;
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (FWD == FWD_MFMA_F32) {
+      const int pbase = rr * W6 + cc;
 #pragma unroll
-    for (int s = 0; s < KK / 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a_reg[s], u6[pbase + toff[s]], acc, 0, 0, 0);
-    const float ulast = u6[pbase + TLAST];
-    acc[0] = fmaf(klast.x, ulast, acc[0]);
-    acc[1] = fmaf(klast.y, ulast, acc[1]);
-    acc[2] = fmaf(klast.z, ulast, acc[2]);
-    acc[3] = fmaf(klast.w, ulast, acc[3]);
+      for (int s = 0; s < KK / 4; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ops.a[s], u6[pbase + ops.toff[s]], acc, 0, 0, 0);
+      const float ulast = u6[pbase + TLAST];
+      acc[0] = fmaf(ops.klast.x, ulast, acc[0]);
+      acc[1] = fmaf(ops.klast.y, ulast, acc[1]);
+      acc[2] = fmaf(ops.klast.z, ulast, acc[2]);
+      acc[3] = fmaf(ops.klast.w, ulast, acc[3]);
+    } else {
+      // window row rr + lk (+ 4 in step 1), columns cc .. cc + 7 from the copy where they are aligned
+      const unsigned* b = u16 + (cc & 1) * SP::COPY_W + (rr + lk) * SP::ROW_W + (cc >> 1);
+      floatx4 hh = {0.0f, 0.0f, 0.0f, 0.0f}, cr = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int o = s * 4 * SP::ROW_W, ot = o + SP::TAIL_W;
+        const u32x4 wh = {b[o], b[o + 1], b[o + 2], b[o + 3]};
+        const u32x4 wt = {b[ot], b[ot + 1], b[ot + 2], b[ot + 3]};
+        const half8 bh = __builtin_bit_cast(half8, wh), bt = __builtin_bit_cast(half8, wt);
+        cr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ops.lo[s], bh, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ops.hi[s], bt, cr, 0, 0, 0);
+        hh = __builtin_amdgcn_mfma_f32_16x16x32_f16(ops.hi[s], bh, hh, 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = fmaf(cr[j], ops.sclo, hh[j] * ops.sc);
+    }
     const int gy = y0 - R + rr, gx = x0 - R + cc;
     bool inimg = true;
     if constexpr (!ALL_IN) inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
@@ -221,8 +284,13 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   // taps of the current chunk, read by broadcast LDS loads so that the FMAs take them from VGPRs
   // (a VALU FMA with an SGPR operand issues at half rate on gfx950)
   constexpr int KAP = 52;                                   // padded adjoint tap stride (16 B rows)
-  __shared__ __attribute__((aligned(16))) float kf_s[KK * NC];   // [t][j]
+  constexpr bool SPLIT = FWD == FWD_MFMA_F16X;
+  constexpr int KF_N = SPLIT ? F16_OPS : KK * NC;           // forward tap words per chunk
+  __shared__ __attribute__((aligned(16))) float kf_s[KF_N];      // [t][j], or the split operands by lane
   __shared__ __attribute__((aligned(16))) float ka_s[NC * KAP];  // [j][t]
+  using SP = SplitPlanes<TW, TH>;
+  __shared__ __attribute__((aligned(16))) unsigned u16w[SPLIT ? SP::WORDS : 1];
+  __shared__ float wmax[SPLIT ? NT / 64 : 1];
 
   const int tid = threadIdx.x;
   const Problem pb = a.pb;
@@ -236,13 +304,16 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   // taps of the next chunk, fetched one chunk ahead (chunk 0: before stage 1) so that their HBM latency
   // is hidden behind the work in between (the BF16 engine, short of registers, fetches at chunk start)
   constexpr bool PREFETCH = FWD != FWD_MFMA_BF16;
-  constexpr int KF_PT = (KK * NC + NT - 1) / NT, KA_PT = (NC * KAP + NT - 1) / NT;
+  constexpr int KF_PT = (KF_N + NT - 1) / NT, KA_PT = (NC * KAP + NT - 1) / NT;
   float kfr[KF_PT], kar[KA_PT];
   auto fetch_taps = [&](int cn) {
 #pragma unroll
     for (int q = 0; q < KF_PT; ++q) {
       const int t = tid + q * NT;
-      kfr[q] = t < KK * NC ? a.kf[(size_t)cn * KK + t] : 0.0f;
+      if constexpr (SPLIT)
+        kfr[q] = t < KF_N ? __uint_as_float(a.kf16[(size_t)(cn / NC) * F16_OPS + t]) : 0.0f;
+      else
+        kfr[q] = t < KF_N ? a.kf[(size_t)cn * KK + t] : 0.0f;
     }
 #pragma unroll
     for (int q = 0; q < KA_PT; ++q) {
@@ -314,6 +385,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   const bool all_in = y0 >= R && y0 + TH + R <= H && x0 >= R && x0 + TW + R <= W;
 
   double accF = 0.0, accG = 0.0, accS1 = 0.0, accS2 = 0.0, accM = 0.0;
+  float usc = 1.0f;   // split-FP16 engine: the tile's scale 2^E of u
 
 
   // ---- stage 1: step + prox on tile + 6 halo -> u6 (ADJ_HALF: u+ = e^{x+} on the tile only, x+
@@ -331,6 +403,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     // the positions of this thread, two at a time: their loads first (invalid positions read pixel 0
     // and are discarded), so that the HBM latency of the block's inputs is paid once per batch
     constexpr int P1 = 2;
+    float umx = 0.0f;   // largest |u| of this thread (split-FP16 engine)
 #pragma unroll 1
     for (int b0 = tid; b0 < H6 * W6; b0 += P1 * NT) {
     int ps[P1];
@@ -379,7 +452,58 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         }
       }
       u6[idx] = uval;
+      if constexpr (SPLIT) umx = fmaxf(umx, fabsf(uval));
     }
+    }
+    if constexpr (SPLIT) {
+      // the tile's scale 2^E (largest |u| / 2^E in [2^13, 2^14)), then u / 2^E split into FP16 heads and
+      // tails in both plane copies, and the zero padding
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) umx = fmaxf(umx, __shfl_xor(umx, o));
+      if ((tid & 63) == 0) wmax[tid >> 6] = umx;
+      __syncthreads();
+      float m = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) m = fmaxf(m, wmax[w]);
+      const int E = __builtin_amdgcn_readfirstlane(min(max(((__float_as_int(m) >> 23) & 0xff) - 127 - 13, -100), 100));
+      const float isc = __int_as_float((127 - E) << 23);
+      _Float16* h = reinterpret_cast<_Float16*>(u16w);
+      constexpr int COPY_H = 2 * SP::COPY_W, ROW_H = 2 * SP::ROW_W;
+      for (int idx = tid; idx < H6 * W6; idx += NT) {
+        const int r = idx / W6, c = idx - r * W6;
+        const float v = u6[idx] * isc;
+        const _Float16 hi = (_Float16)v;
+        const _Float16 lo = (_Float16)((v - (float)hi) * 4096.0f);
+        _Float16* q = h + r * ROW_H + c;
+        q[0] = hi;
+        q[SP::COLS] = lo;
+        if (c > 0) {
+          q[COPY_H - 1] = hi;
+          q[COPY_H - 1 + SP::COLS] = lo;
+        }
+      }
+      // padding: copy 0 columns W6.., copy 1 columns W6 - 1.. of every row; the last row of both copies
+      constexpr int NP0 = SP::COLS - W6, NPR = 2 * (2 * NP0 + 1), NLAST = 4 * SP::COLS;
+      for (int i = tid; i < H6 * NPR + NLAST; i += NT) {
+        int cp, row, part, col;
+        if (i < H6 * NPR) {
+          row = i / NPR;
+          int q = i - row * NPR;
+          part = q & 1;
+          q >>= 1;
+          cp = q >= NP0;
+          col = cp ? W6 - 1 + (q - NP0) : W6 + q;
+        } else {
+          int q = i - H6 * NPR;
+          cp = q / (2 * SP::COLS);
+          q -= cp * 2 * SP::COLS;
+          part = q / SP::COLS;
+          col = q - part * SP::COLS;
+          row = H6;
+        }
+        h[cp * COPY_H + row * ROW_H + part * SP::COLS + col] = (_Float16)0.0f;
+      }
+      usc = __int_as_float((127 + E) << 23);
     }
   }
 
@@ -434,7 +558,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     if constexpr (PREFETCH) {
 #pragma unroll
       for (int q = 0; q < KF_PT; ++q)
-        if (tid + q * NT < KK * NC) kf_s[tid + q * NT] = kfr[q];
+        if (tid + q * NT < KF_N) kf_s[tid + q * NT] = kfr[q];
 #pragma unroll
       for (int q = 0; q < KA_PT; ++q)
         if (tid + q * NT < NC * KAP) ka_s[tid + q * NT] = kar[q];
@@ -535,36 +659,47 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         }
         if (own) accF += (double)e;
       }
-    } else if constexpr (FWD == FWD_MFMA_F32) {
+    } else if constexpr (FWD == FWD_MFMA_F32 || FWD == FWD_MFMA_F16X) {
       // ---- stage 2 (matrix cores): per group of 16 consecutive R3 positions,
-      // Y^T[16 filters x 16 positions] = Kflip^T[16 x 48 taps] . X[48 taps x 16 positions] with
-      // twelve v_mfma_f32_16x16x4f32, and the last tap (48) added on the VALU.  Lane (m = lane % 16,
+      // Y^T[16 filters x 16 positions] = Kflip^T[16 x taps] . X[taps x 16 positions].  FP32 engine:
+      // twelve v_mfma_f32_16x16x4f32 over taps 0..47 and the last tap (48) on the VALU; lane (m = lane % 16,
       // k = lane / 16) holds the A value Kflip[filter m][tap 4s + k] and the B value u6 at tap 4s + k of
-      // position m; the result lands as y for position m, filters 4k .. 4k + 3.
+      // position m.  Split-FP16 engine: the operands of ForwardOps<FWD_MFMA_F16X>, staged per lane in
+      // kf_s.  Either way the result lands as y for position m, filters 4k .. 4k + 3.
       const int lane = tid & 63, wave = tid >> 6, lm = lane & 15, lk = lane >> 4;
-      constexpr int NS4 = KK / 4;                  // 12 MFMA steps of 4 taps; KK = 4 NS4 + 1
-      float a_reg[NS4];
-      int toff[NS4];
+      ForwardOps<FWD> ops;
+      if constexpr (FWD == FWD_MFMA_F32) {
+        constexpr int NS4 = KK / 4;                  // 12 MFMA steps of 4 taps; KK = 4 NS4 + 1
 #pragma unroll
-      for (int s = 0; s < NS4; ++s) {
-        const int t = 4 * s + lk;
-        a_reg[s] = kf_s[t * NC + lm];
-        // taps 4s + k and 4(s + 7) + k are 28 = 4 KS apart: 4 rows of u6 in every lane, so that the
-        // loads of steps s and s + 7 share an address register (the difference is an immediate)
-        toff[s] = s < KS ? (t / KS) * W6 + (t % KS) : toff[s - KS] + 4 * W6;
+        for (int s = 0; s < NS4; ++s) {
+          const int t = 4 * s + lk;
+          ops.a[s] = kf_s[t * NC + lm];
+          // taps 4s + k and 4(s + 7) + k are 28 = 4 KS apart: 4 rows of u6 in every lane, so that the
+          // loads of steps s and s + 7 share an address register (the difference is an immediate)
+          ops.toff[s] = s < KS ? (t / KS) * W6 + (t % KS) : ops.toff[s - KS] + 4 * W6;
+        }
+        ops.klast = *reinterpret_cast<const float4*>(kf_s + (KK - 1) * NC + 4 * lk);  // tap 48, filters 4k..
+      } else {
+        const u32x4* src = reinterpret_cast<const u32x4*>(kf_s) + lane * 4;   // [step][head, tail]
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          ops.hi[s] = __builtin_bit_cast(half8, src[2 * s]);
+          ops.lo[s] = __builtin_bit_cast(half8, src[2 * s + 1]);
+        }
+        ops.sc = usc;
+        ops.sclo = usc * (1.0f / 4096.0f);
       }
-      const float4 klast = *reinterpret_cast<const float4*>(kf_s + (KK - 1) * NC + 4 * lk);  // tap 48, filters 4k..
       float thl[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) thl[j] = (4 * lk + j < ncur ? a.theta[c0 + 4 * lk + j] : 0.0f) * 0.6931471805599453f;
       // one position group per pass: with four waves per SIMD the other waves' chains fill the
       // matrix pipe while this one waits for its predecessor
       float* zb = UNF == FWD_HALF ? a.zbuf + (size_t)c0 * a.zstride + im.off : nullptr;
-      const float ef = all_in ? mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, true>(
-                                      u6, zp, a_reg, toff, klast, thl, wave, lm, lk, y0, x0, H, W,
+      const float ef = all_in ? mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, true, FWD>(
+                                      u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W,
                                       bc == PERIODIC, zb, a.zstride, ncur)
-                                : mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, false>(
-                                      u6, zp, a_reg, toff, klast, thl, wave, lm, lk, y0, x0, H, W,
+                                : mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, false, FWD>(
+                                      u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W,
                                       bc == PERIODIC, zb, a.zstride, ncur);
       accF += (double)ef;
     } else {

@@ -49,3 +49,12 @@ def test_host_only_calls():
     p.beta = 1.5
     st = foe.lib.foe_create(ctypes.byref(p), k, th, None, ctypes.byref(h))
     assert st == foe.EINVAL and b"beta" in foe.lib.foe_last_error()
+    # the split-FP16 engine takes taps below 2^14 only (AUTO falls back to FP32 operands instead)
+    p.beta = 0.8
+    p.engine = foe.ENGINE_MFMA_SPLIT
+    k[5] = 20000.0
+    st = foe.lib.foe_create(ctypes.byref(p), k, th, None, ctypes.byref(h))
+    assert st == foe.EINVAL and b"split-FP16" in foe.lib.foe_last_error()
+    p.engine = 4
+    st = foe.lib.foe_create(ctypes.byref(p), k, th, None, ctypes.byref(h))
+    assert st == foe.EINVAL and b"bad engine" in foe.lib.foe_last_error()

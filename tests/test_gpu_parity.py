@@ -28,7 +28,7 @@ def _gpu(t, dev):
     return torch.from_numpy(np.ascontiguousarray(t, dtype=np.float32)).to(dev)
 
 
-ENGINES = [1, 2]   # FOE_ENGINE_VALU, FOE_ENGINE_MFMA (forward bank on matrix cores)
+ENGINES = [1, 2, 3]   # FOE_ENGINE_VALU, FOE_ENGINE_MFMA, FOE_ENGINE_MFMA_SPLIT (forward bank on matrix cores)
 
 
 @pytest.mark.parametrize("engine", ENGINES)

@@ -28,7 +28,8 @@ def _config1_fixed_alpha(pr, bank, theta, beta=0.8):
     return 1.9 * (1 - beta) / L_hat
 
 
-def test_config1_fixed_step_every_step_and_psnr():
+@pytest.mark.parametrize("engine", [2, 3])   # FP32 operands, split-FP16 operands
+def test_config1_fixed_step_every_step_and_psnr(engine):
     torch, dev = torch_dev()
     pr = synth.config1()
     bank, theta = synth.dct_bank(), synth.theta_weights(1)
@@ -37,7 +38,7 @@ def test_config1_fixed_step_every_step_and_psnr():
     ref = oracle.ipiano(po, pr.f, bank, theta, 100)
     assert ref.status == oracle.OK
     s = make_solver(64, 64, bank, theta, lambda1=pr.lam1, lambda2=pr.lam2, step_mode=1, alpha_fixed=alpha,
-                    max_iters=100)
+                    max_iters=100, engine=engine)
     out = s.solve(_gpu(pr.f, dev))
     u = out.u.cpu().numpy()
     d_psnr = abs(synth.psnr(u, pr.clean) - synth.psnr(ref.u(), pr.clean))
@@ -121,15 +122,16 @@ def test_config1_idiv_convex_fixed_step():
     s.close()
 
 
-def test_config2_full_run_against_stored_oracle():
+@pytest.mark.parametrize("engine", [2, 3])   # FP32 operands, split-FP16 operands
+def test_config2_full_run_against_stored_oracle(engine):
     """512x512, L = 1, backtracking, 300 iterations: final PSNR within 0.01 dB of the FP64 oracle
-    (stored by tests/golden/make_golden.py, which calls only the oracle)."""
+    (stored by tests/golden/make_golden.py, which calls only the oracle), for both matrix-core engines."""
     path = os.path.join(GOLDEN, "config2_oracle.json")
     gold = json.load(open(path))
     torch, dev = torch_dev()
     pr = synth.config2()
     bank, theta = synth.dct_bank(), synth.theta_weights(2)
-    s = make_solver(512, 512, bank, theta, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=300)
+    s = make_solver(512, 512, bank, theta, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=300, engine=engine)
     out = s.solve(_gpu(pr.f, dev))
     u = out.u.cpu().numpy()
     psnr = synth.psnr(u, pr.clean)

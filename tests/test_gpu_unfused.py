@@ -17,7 +17,7 @@ def _gpu(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
 
 
-@pytest.mark.parametrize("engine", [1, 2])
+@pytest.mark.parametrize("engine", [1, 2, 3])
 @pytest.mark.parametrize("model", [oracle.COMBINED, oracle.LOG, oracle.IDIV])
 @pytest.mark.parametrize("bc", [oracle.SYMMETRIC, oracle.ZERO, oracle.PERIODIC])
 @pytest.mark.parametrize("shape", [(8, 8), (37, 64), (66, 34), (100, 131), (33, 257)])
