@@ -7,6 +7,10 @@ backtracking, output) on synthetic input resident in HBM.  Prints one JSON line:
                 (per-launch HIP event pairs on the solver stream), against the FP32 peak; traffic =
                 HBM bytes per launch from the committed hardware-counter summary when it was taken
                 on the current kernel sources, else null
+  engines       the solver's default forward bank is the split-FP16 matrix-core engine (each FP32
+                operand as an FP16 head plus a scaled FP16 tail, exact products, FP32 accumulation;
+                the parity bars of the FP32 path); the same workload on the FP32-operand matrix-core
+                engine is timed beside it (fp32_operand_engine)
   cpu_baseline  the FP64 oracle on the host cores over a bounded sample of the same workload
   forms         time-to-PSNR of the batched, BF16 and warm-started forms against the plain FP32
                 solver on their own workloads (the wall time to reach the plain run's final PSNR
@@ -31,6 +35,11 @@ import numpy as np  # noqa: E402
 
 METRIC = "Mpixel-iters/s iPiano-FoE on 1 GPU; time-to-PSNR vs plain FP32; roofline %"
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 peak, vector and matrix cores alike
+PEAK_F16_MFMA_TFLOPS = 2500.0  # MI355X published dense FP16 matrix peak
+# the split forward bank issues 3 FP16 products per FP32 product over 64 tap slots for 49 taps
+SPLIT_FWD_PEAK = PEAK_F16_MFMA_TFLOPS / 3.0 * 49.0 / 64.0
+# forward bank at that rate and adjoint bank (same flops) at the FP32 peak
+MIXED_PEAK_TFLOPS = 2.0 / (1.0 / SPLIT_FWD_PEAK + 1.0 / PEAK_FP32_TFLOPS)
 NF, KK = 48, 49
 FLOP_PER_PX_TRIAL = 2 * 2 * NF * KK   # forward bank on x+ and adjoint bank, one FMA = 2 flop
 KERNEL_SOURCES = ["common.hpp", "device_math.hpp", "kernels_trial.hpp", "foe_lib.hip"]   # kernels and their launch shapes
@@ -422,9 +431,30 @@ def main():
     traffic = measured_traffic()
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "kernel": "foe_trial_kernel (forward bank on FP32 MFMA, adjoint on VALU)",
+                "kernel": "foe_trial_kernel (forward bank on split-FP16 MFMA with FP32 accumulation, adjoint on "
+                          "FP32 VALU)",
                 "ms_per_launch": round(ms_launch, 5), "flop_per_launch": flop,
+                "frac_mixed_peak": round(achieved / MIXED_PEAK_TFLOPS, 4),
+                "mixed_peak_tflops": round(MIXED_PEAK_TFLOPS, 1),
                 "kernel_source_hash": kernel_source_hash()}
+    s.close()
+    # the same workload on the FP32-operand matrix-core engine
+    p32 = foe.default_params(H, W, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=args.iters, looks=1,
+                             fusion=1 if args.unfused else 0, engine=foe.ENGINE_MFMA)
+    s32 = foe.Solver(p32, bank, theta, stream=stream)
+    s32.solve(f, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it32 = 0
+    for k in range(args.steps):
+        it32 += s32.solve(f, out=out).summary["iters_done"]
+    torch.cuda.synchronize()
+    dt32 = time.perf_counter() - t0
+    fp32_engine = {"value": round(H * W * it32 / dt32 / 1e6, 2), "ms_per_step": round(dt32 * 1e3 / args.steps, 4),
+                   "ms_per_launch": round(s32.profile_trial(50), 5),
+                   "psnr_db": round(synth.psnr(out.cpu().numpy(), pr.clean), 4)}
+    s32.close()
+    log(f"bench: FP32-operand engine {fp32_engine}")
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.ones(n, device=dev)
@@ -442,10 +472,12 @@ def main():
                                "48 DCT 7x7 filters, SYMMETRIC boundary, beta 0.8, backtracking, "
                                f"{args.iters} iterations per step" + (", gradient unfused" if args.unfused else ""),
                    "pixels": H * W, "iterations": args.iters, "trials_per_iter": round(trials_total / iters_total, 4),
-                   "psnr_db": round(psnr, 4), "ssim": round(ssim, 5)},
+                   "psnr_db": round(psnr, 4), "ssim": round(ssim, 5),
+                   "forward_bank": "split-FP16 MFMA: FP32 operand = FP16 head + FP16 tail / 4096, three exact "
+                                   "FP16 products per FP32 product, FP32 accumulation"},
         "roofline": roofline,
+        "fp32_operand_engine": fp32_engine,
     }
-    s.close()
     if not args.no_forms:
         forms = {}
         for name, fn in (("batched", form_batched), ("bf16", form_bf16), ("warm_start", form_warm),

@@ -79,30 +79,35 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* red, dou
   }
 }
 
-// The three mirror terms of one fold item from its z lines and tap lines (see the mirror-term comment
-// below): Z_r = zb + r zls + t ZT, K_m = kb + m kls + t KT for t = 0..6; v(d) = sum_{r <= 2 - d}
-// <K_{d+r}, Z_r>.  The strides along the lines are template constants so that every load of a
-// line takes an immediate offset from one address register.
-template <int ZT, int KT>
-__device__ __forceinline__ void fold_lines(const float* zb, int zls, const float* kb, int kls, float& v0, float& v1,
-                                           float& v2) {
-  float Z[R][KS], K[R][KS];
+// The mirror terms of FB consecutive positions along an edge for one filter: v_i(d) = sum_{r <= 2 - d}
+// <K_{d+r}, Z_r[i .. i + 6]> with Z_r[s] = zb[r ZL + s ZS] (s = 0 .. FB + 5) and K_m[t] = kb[m KL + t KT],
+// added to out[(i R + d) NC] (each partial has one writer per chunk).  The z lines slide through
+// registers, the tap lines are loaded once.
+template <int FB, int NC, int ZS, int ZL, int KT, int KL>
+__device__ __forceinline__ void fold_block(const float* zb, const float* kb, float* out) {
+  float Z[R][FB + KS - 1], K[R][KS];
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int s = 0; s < FB + KS - 1; ++s) Z[r][s] = zb[r * ZL + s * ZS];
+#pragma unroll
+    for (int t = 0; t < KS; ++t) K[r][t] = kb[r * KL + t * KT];
+  }
+#pragma unroll
+  for (int i = 0; i < FB; ++i) {
+    float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
 #pragma unroll
     for (int t = 0; t < KS; ++t) {
-      Z[r][t] = zb[r * zls + t * ZT];
-      K[r][t] = kb[r * kls + t * KT];
+      v0 = fmaf(K[0][t], Z[0][i + t], v0);
+      v0 = fmaf(K[1][t], Z[1][i + t], v0);
+      v0 = fmaf(K[2][t], Z[2][i + t], v0);
+      v1 = fmaf(K[1][t], Z[0][i + t], v1);
+      v1 = fmaf(K[2][t], Z[1][i + t], v1);
+      v2 = fmaf(K[2][t], Z[0][i + t], v2);
     }
-  v0 = v1 = v2 = 0.0f;
-#pragma unroll
-  for (int t = 0; t < KS; ++t) {
-    v0 = fmaf(K[0][t], Z[0][t], v0);
-    v0 = fmaf(K[1][t], Z[1][t], v0);
-    v0 = fmaf(K[2][t], Z[2][t], v0);
-    v1 = fmaf(K[1][t], Z[0][t], v1);
-    v1 = fmaf(K[2][t], Z[1][t], v1);
-    v2 = fmaf(K[2][t], Z[0][t], v2);
+    out[(i * R + 0) * NC] += v0;
+    out[(i * R + 1) * NC] += v1;
+    out[(i * R + 2) * NC] += v2;
   }
 }
 
@@ -154,7 +159,7 @@ struct SplitPlanes {
 // the own positions to HBM (zb = plane of the chunk's first filter at the image, zstride apart).
 // Lanes past the last position compute position 0 and store its value there again: the same bits
 // as the lane that owns it, so the duplicate store is harmless.
-template <int TW, int TH, int NC, int GS, int FUSION, bool ALL_IN, int FWD>
+template <int TW, int TH, int NC, int GS, int FUSION, bool ALL_IN, int FWD, bool UNIT = false>
 __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsigned* u16, float* zp,
                                                     const ForwardOps<FWD>& ops, const float (&thl)[4], int g0, int lm,
                                                     int lk, int y0, int x0, int H, int W, bool periodic, float* zb,
@@ -166,6 +171,12 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
   constexpr int TLAST = (KS - 1) * W6 + (KS - 1);
   constexpr int NFULL = PLANE / 16;                               // groups with no position past the plane
   int p = g0 * 16 + lm, r = p / W3, c = p - r * W3;
+  // split-FP16 engine: word offset of the B operands of this lane (window row r + lk, columns c ..
+  // c + 7, in the copy where they are aligned).  A pass advances the position by STEP: DR rows and DC
+  // columns, or one row more and DC - W3 columns when the column wraps; DC and W3 are even, so the
+  // column parity and with it the copy stay the same and the offset advances by a constant.
+  static_assert(DC % 2 == 0 && W3 % 2 == 0, "a pass keeps the column parity");
+  int bw = (c & 1) * SP::COPY_W + (r + lk) * SP::ROW_W + (c >> 1);
   float ef = 0.0f;
   // one group: PARTIAL = the last group, whose lanes past the plane take position 0
   auto group = [&](auto partial_tag) {
@@ -185,7 +196,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       acc[3] = fmaf(ops.klast.w, ulast, acc[3]);
     } else {
       // window row rr + lk (+ 4 in step 1), columns cc .. cc + 7 from the copy where they are aligned
-      const unsigned* b = u16 + (cc & 1) * SP::COPY_W + (rr + lk) * SP::ROW_W + (cc >> 1);
+      const unsigned* b = u16 + (inr ? bw : lk * SP::ROW_W);
       floatx4 hh = {0.0f, 0.0f, 0.0f, 0.0f}, cr = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
@@ -198,7 +209,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
         hh = __builtin_amdgcn_mfma_f32_16x16x32_f16(ops.hi[s], bh, hh, 0, 0, 0);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j] = fmaf(cr[j], ops.sclo, hh[j] * ops.sc);
+      for (int j = 0; j < 4; ++j) acc[j] = UNIT ? fmaf(cr[j], 1.0f / 4096.0f, hh[j]) : fmaf(cr[j], ops.sclo, hh[j] * ops.sc);
     }
     const int gy = y0 - R + rr, gx = x0 - R + cc;
     bool inimg = true;
@@ -219,10 +230,12 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
     p += STEP;
     c += DC;
     r += DR;
-    if (c >= W3) {
+    const bool wrap = c >= W3;
+    if (wrap) {
       c -= W3;
       r += 1;
     }
+    if constexpr (FWD == FWD_MFMA_F16X) bw += wrap ? (DR + 1) * SP::ROW_W + (DC - W3) / 2 : DR * SP::ROW_W + DC / 2;
   };
   int g = g0;
 #pragma unroll 1
@@ -239,11 +252,11 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
 // the tap lines 4 + d .. 6 (low edge) or 2 - d .. 0 (high edge).  With Z_r the z line at distance r
 // from the edge and K_m the tap line 4 + m (low) or 2 - m (high), both taken along the edge,
 //   v(d) = sum_{r=0}^{2-d} <K_{d+r}, Z_r>   (7 products per line pair).
-// One fold item is one position along an edge and one filter: it forms v(0), v(1), v(2).  Items of
-// the y edges run over the TW columns of the tile; items of the x edges run over the TH rows of the
-// tile and, for the corners, over the extended rows -1-i (target row i) and H+i (target row H-1-i)
-// whose target row lies in the tile: a corner sample then is an x-edge item whose window rows off
-// the image read zeros.
+// One fold item is one filter and FB consecutive positions along an edge (fold_block): it forms v(0),
+// v(1), v(2) of each.  Items of the y edges run over the TW columns of the tile, items of the x edges
+// over its TH rows; one more item per filter and corner row takes the extended rows -1-i (target row
+// i) and H+i (target row H-1-i) of an x edge whose target row lies in the tile: a corner sample then
+// is an x-edge position whose window rows off the image read zeros.
 // Layout slots (partials fpart[(slot * 3 + d) * NC + j] in the epilogue):
 //   [0, TW) y-low, [TW, 2TW) y-high, then per x edge TH + 6 slots: the tile rows, the 3 low-corner
 //   rows (i = 0..2), the 3 high-corner rows (i = 0..2).
@@ -465,7 +478,11 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       float m = 0.0f;
 #pragma unroll
       for (int w = 0; w < NT / 64; ++w) m = fmaxf(m, wmax[w]);
-      const int E = __builtin_amdgcn_readfirstlane(min(max(((__float_as_int(m) >> 23) & 0xff) - 127 - 13, -100), 100));
+      // no scaling (E = 0) when the largest |u| lies in [2^-4, 2^14): the heads stay below 2^14 and the
+      // absolute resolution of the split (2^-36) is far below the FP32 rounding of the largest terms
+      const int E = m >= 0.0625f && m < 16384.0f
+                        ? 0
+                        : __builtin_amdgcn_readfirstlane(min(max(((__float_as_int(m) >> 23) & 0xff) - 127 - 13, -100), 100));
       const float isc = __int_as_float((127 - E) << 23);
       _Float16* h = reinterpret_cast<_Float16*>(u16w);
       constexpr int COPY_H = 2 * SP::COPY_W, ROW_H = 2 * SP::ROW_W;
@@ -507,19 +524,23 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     }
   }
 
-  // ---- fold tiles: clear the fold partials and count the fold items: positions
-  // along each live edge (y edges: TW columns; x edges: TH rows + the corner rows whose target row
-  // lies in the tile) times NC filters, filter index fastest
+  // ---- fold tiles: clear the fold partials and count the fold items, filter index fastest: blocks of
+  // FB positions along each live edge (y edges: the TW columns; x edges: the TH rows), then single
+  // positions for the corner rows of the x edges whose target row lies in the tile
   const bool e_ylo = fold && y0 == 0, e_yhi = fold && y0 + TH >= H - (R - 1);
   const bool e_xlo = fold && x0 == 0, e_xhi = fold && x0 + TW >= W - (R - 1);
   const int c_lo = y0 == 0 ? R : 0;                               // low-corner rows i = 0..2
   const int c_h0 = max(0, H - y0 - TH), c_h1 = min(R - 1, H - 1 - y0);  // high-corner rows i
   const int c_hn = e_yhi ? max(0, c_h1 - c_h0 + 1) : 0;
-  const int npx = TH + c_lo + c_hn;
-  const int f_s1 = e_ylo ? NC * TW : 0;                 // item starts of the y-high, x-low, x-high
-  const int f_s2 = f_s1 + (e_yhi ? NC * TW : 0);        // edges, and the item count
-  const int f_s3 = f_s2 + (e_xlo ? NC * npx : 0);
-  const int n_items = f_s3 + (e_xhi ? NC * npx : 0);
+  constexpr int FB = 2;                                 // positions per block item
+  static_assert(TW % FB == 0 && TH % FB == 0, "fold blocks tile the edges");
+  const int ncr = c_lo + c_hn;                          // corner rows per x edge
+  const int f_y1 = e_ylo ? NC * (TW / FB) : 0;          // item starts: y-high blocks, x-low blocks,
+  const int f_x0 = f_y1 + (e_yhi ? NC * (TW / FB) : 0); // x-high blocks, x-low corner rows, x-high
+  const int f_x1 = f_x0 + (e_xlo ? NC * (TH / FB) : 0); // corner rows; and the item count
+  const int f_c0 = f_x1 + (e_xhi ? NC * (TH / FB) : 0);
+  const int f_c1 = f_c0 + (e_xlo ? NC * ncr : 0);
+  const int n_items = f_c1 + (e_xhi ? NC * ncr : 0);
   if (fold)
     for (int i = tid; i < NSLOT * R * NC; i += NT) fpart[i] = 0.0f;
 
@@ -695,12 +716,17 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       // one position group per pass: with four waves per SIMD the other waves' chains fill the
       // matrix pipe while this one waits for its predecessor
       float* zb = UNF == FWD_HALF ? a.zbuf + (size_t)c0 * a.zstride + im.off : nullptr;
-      const float ef = all_in ? mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, true, FWD>(
-                                      u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W,
-                                      bc == PERIODIC, zb, a.zstride, ncur)
-                                : mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, false, FWD>(
-                                      u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W,
-                                      bc == PERIODIC, zb, a.zstride, ncur);
+      float ef;
+      if (FWD == FWD_MFMA_F16X && usc == 1.0f)
+        ef = all_in ? mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, true, FWD, true>(
+                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur)
+                    : mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, false, FWD, true>(
+                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur);
+      else
+        ef = all_in ? mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, true, FWD>(
+                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur)
+                    : mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, false, FWD>(
+                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur);
       accF += (double)ef;
     } else {
       // ---- stage 2: forward bank on tile + 3 halo; one row of taps of 8 filters (in SGPRs) per pass
@@ -793,68 +819,72 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       }
     }
     // the fold items of this thread (all threads take part; a pass of its own after the regular
-    // blocks, whose window registers are dead by then).  Each item owns its 3 partials.
+    // blocks, whose window registers are dead by then).  Each item owns its partials.
     if (fold) {
 #pragma unroll 1
       for (int it = tid; it < n_items; it += NT) {
-        const int e = (it >= f_s1) + (it >= f_s2) + (it >= f_s3);   // 0 y-low 1 y-high 2 x-low 3 x-high
-        const int loc = it - (e == 0 ? 0 : e == 1 ? f_s1 : e == 2 ? f_s2 : f_s3);
-        const int j = loc & (NC - 1), p = loc / NC;
-        if (j >= ncur) continue;
-        const float* zpl = zp + j * PLANE;
-        const float* kj = ka_s + j * KAP;
-        float v0, v1, v2;
-        int slot;
-        if (e < 2) {
-          // y edge, position = tile column p: z lines are rows, taps run along a tap row
-          slot = e * TW + p;
-          const int zr0 = e == 0 ? R : H - 1 - y0 + R;           // plane row of the edge line
-          fold_lines<1, 1>(zpl + zr0 * W3 + p, e == 0 ? W3 : -W3,  // + t: column x0 + p - 3 + t
-                           kj + (e == 0 ? (R + 1) * KS : (R - 1) * KS), e == 0 ? KS : -KS, v0, v1, v2);
+        if (it < f_x0) {
+          // y edge block, tile columns p0 .. p0 + FB - 1: z lines are plane rows, taps run along tap rows
+          const bool lo = it < f_y1;
+          const int loc = it - (lo ? 0 : f_y1), j = loc & (NC - 1), p0 = (loc / NC) * FB;
+          if (j >= ncur) continue;
+          float* out = fpart + ((lo ? 0 : TW) + p0) * R * NC + j;
+          if (lo)
+            fold_block<FB, NC, 1, W3, 1, KS>(zp + j * PLANE + R * W3 + p0, ka_s + j * KAP + (R + 1) * KS, out);
+          else
+            fold_block<FB, NC, 1, -W3, 1, -KS>(zp + j * PLANE + (H - 1 - y0 + R) * W3 + p0,
+                                               ka_s + j * KAP + (R - 1) * KS, out);
+        } else if (it < f_c0) {
+          // x edge block, tile rows p0 .. p0 + FB - 1: z lines are plane columns, taps run down tap columns
+          const bool lo = it < f_x1;
+          const int loc = it - (lo ? f_x0 : f_x1), j = loc & (NC - 1), p0 = (loc / NC) * FB;
+          if (j >= ncur) continue;
+          float* out = fpart + (2 * TW + (lo ? 0 : NPX) + p0) * R * NC + j;
+          if (lo)
+            fold_block<FB, NC, W3, 1, KS, 1>(zp + j * PLANE + p0 * W3 + R, ka_s + j * KAP + R + 1, out);
+          else
+            fold_block<FB, NC, W3, -1, KS, -1>(zp + j * PLANE + p0 * W3 + W - 1 - x0 + R, ka_s + j * KAP + R - 1,
+                                               out);
         } else {
-          // x edge, position = extended row gy: z lines are columns, taps run down a tap column
-          const int q = p - TH;
+          // a corner row (-1 - i or H + i) of an x edge: window rows outside the plane are off the image
+          // (rows < 0 for the low corners, >= H for the high ones); they read the plane's first / last
+          // row, which is off the image too
+          const int e = it < f_c1 ? 2 : 3;
+          const int loc = it - (e == 2 ? f_c0 : f_c1), j = loc & (NC - 1), q = loc / NC;
+          if (j >= ncur) continue;
           const int zc0 = e == 2 ? R : W - 1 - x0 + R;            // plane column of the edge line
           const int zls = e == 2 ? 1 : -1;
-          const float* kb = kj + (e == 2 ? R + 1 : R - 1);
+          const float* zpl = zp + j * PLANE;
+          const float* kb = ka_s + j * KAP + (e == 2 ? R + 1 : R - 1);
           const int kls = e == 2 ? 1 : -1;
-          if (q < 0) {
-            // a row of the tile: window rows p .. p + 6 of the plane
-            slot = 2 * TW + (e - 2) * NPX + p;
-            fold_lines<W3, KS>(zpl + p * W3 + zc0, zls, kb, kls, v0, v1, v2);
-          } else {
-            // a corner row (-1 - i or H + i): window rows outside the plane are off the image (rows < 0
-            // for the low corners, >= H for the high ones); they read the plane's first / last row,
-            // which is off the image too
-            const int gy = q < c_lo ? -1 - q : H + c_h0 + q - c_lo;
-            slot = 2 * TW + (e - 2) * NPX + (q < c_lo ? TH + q : TH + R + c_h0 + q - c_lo);
-            const int prow = gy - y0;                              // plane row of window row 0
-            float Z[R][KS], K[R][KS];
+          const int gy = q < c_lo ? -1 - q : H + c_h0 + q - c_lo;
+          const int slot = 2 * TW + (e - 2) * NPX + (q < c_lo ? TH + q : TH + R + c_h0 + q - c_lo);
+          const int prow = gy - y0;                              // plane row of window row 0
+          float Z[R][KS], K[R][KS];
 #pragma unroll
-            for (int t = 0; t < KS; ++t) {
-              const int ro = min(max(prow + t, 0), H3 - 1) * W3;
+          for (int t = 0; t < KS; ++t) {
+            const int ro = min(max(prow + t, 0), H3 - 1) * W3;
 #pragma unroll
-              for (int r = 0; r < R; ++r) {
-                Z[r][t] = zpl[zc0 + ro + r * zls];
-                K[r][t] = kb[r * kls + t * KS];
-              }
-            }
-            v0 = v1 = v2 = 0.0f;
-#pragma unroll
-            for (int t = 0; t < KS; ++t) {
-              v0 = fmaf(K[0][t], Z[0][t], v0);
-              v0 = fmaf(K[1][t], Z[1][t], v0);
-              v0 = fmaf(K[2][t], Z[2][t], v0);
-              v1 = fmaf(K[1][t], Z[0][t], v1);
-              v1 = fmaf(K[2][t], Z[1][t], v1);
-              v2 = fmaf(K[2][t], Z[0][t], v2);
+            for (int r = 0; r < R; ++r) {
+              Z[r][t] = zpl[zc0 + ro + r * zls];
+              K[r][t] = kb[r * kls + t * KS];
             }
           }
+          float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+#pragma unroll
+          for (int t = 0; t < KS; ++t) {
+            v0 = fmaf(K[0][t], Z[0][t], v0);
+            v0 = fmaf(K[1][t], Z[1][t], v0);
+            v0 = fmaf(K[2][t], Z[2][t], v0);
+            v1 = fmaf(K[1][t], Z[0][t], v1);
+            v1 = fmaf(K[2][t], Z[1][t], v1);
+            v2 = fmaf(K[2][t], Z[0][t], v2);
+          }
+          float* fo = fpart + slot * R * NC + j;
+          fo[0] += v0;
+          fo[NC] += v1;
+          fo[2 * NC] += v2;
         }
-        float* fo = fpart + slot * R * NC + j;
-        fo[0] += v0;
-        fo[NC] += v1;
-        fo[2 * NC] += v2;
       }
     }
     __syncthreads();
