@@ -149,6 +149,21 @@ struct SplitPlanes {
   static constexpr int TAIL_W = COLS / 2;        // word offset of the tail row
 };
 
+// Writes v (= u6[r][c] / 2^E) as its FP16 head and 4096-scaled FP16 tail into both plane copies.
+template <int TW, int TH>
+__device__ __forceinline__ void split_store(unsigned* u16w, int r, int c, float v) {
+  using SP = SplitPlanes<TW, TH>;
+  const _Float16 hi = (_Float16)v;
+  const _Float16 lo = (_Float16)((v - (float)hi) * 4096.0f);
+  _Float16* q = reinterpret_cast<_Float16*>(u16w) + r * 2 * SP::ROW_W + c;
+  q[0] = hi;
+  q[SP::COLS] = lo;
+  if (c > 0) {   // copy 1 holds column c at c - 1
+    q[2 * SP::COPY_W - 1] = hi;
+    q[2 * SP::COPY_W - 1 + SP::COLS] = lo;
+  }
+}
+
 // One chunk of the FP32 matrix-core forward bank on the R3 region of a TW x TH tile: the position
 // groups g0, g0 + GS, ... (16 consecutive positions each, GS groups apart).  Per group, twelve
 // v_mfma_f32_16x16x4f32 take taps 0..47 (lane (m, k): A = filter m at tap 4s + k, B = u6 at tap
@@ -465,41 +480,17 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         }
       }
       u6[idx] = uval;
-      if constexpr (SPLIT) umx = fmaxf(umx, fabsf(uval));
+      if constexpr (SPLIT) {
+        umx = fmaxf(umx, fabsf(uval));
+        split_store<TW, TH>(u16w, r, c, uval);
+      }
     }
     }
     if constexpr (SPLIT) {
-      // the tile's scale 2^E (largest |u| / 2^E in [2^13, 2^14)), then u / 2^E split into FP16 heads and
-      // tails in both plane copies, and the zero padding
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) umx = fmaxf(umx, __shfl_xor(umx, o));
-      if ((tid & 63) == 0) wmax[tid >> 6] = umx;
-      __syncthreads();
-      float m = 0.0f;
-#pragma unroll
-      for (int w = 0; w < NT / 64; ++w) m = fmaxf(m, wmax[w]);
-      // no scaling (E = 0) when the largest |u| lies in [2^-4, 2^14): the heads stay below 2^14 and the
-      // absolute resolution of the split (2^-36) is far below the FP32 rounding of the largest terms
-      const int E = m >= 0.0625f && m < 16384.0f
-                        ? 0
-                        : __builtin_amdgcn_readfirstlane(min(max(((__float_as_int(m) >> 23) & 0xff) - 127 - 13, -100), 100));
-      const float isc = __int_as_float((127 - E) << 23);
+      // the planes were written unscaled (E = 0); the zero padding, and this wave's largest |u| for the
+      // check after the barrier below
       _Float16* h = reinterpret_cast<_Float16*>(u16w);
       constexpr int COPY_H = 2 * SP::COPY_W, ROW_H = 2 * SP::ROW_W;
-      for (int idx = tid; idx < H6 * W6; idx += NT) {
-        const int r = idx / W6, c = idx - r * W6;
-        const float v = u6[idx] * isc;
-        const _Float16 hi = (_Float16)v;
-        const _Float16 lo = (_Float16)((v - (float)hi) * 4096.0f);
-        _Float16* q = h + r * ROW_H + c;
-        q[0] = hi;
-        q[SP::COLS] = lo;
-        if (c > 0) {
-          q[COPY_H - 1] = hi;
-          q[COPY_H - 1 + SP::COLS] = lo;
-        }
-      }
-      // padding: copy 0 columns W6.., copy 1 columns W6 - 1.. of every row; the last row of both copies
       constexpr int NP0 = SP::COLS - W6, NPR = 2 * (2 * NP0 + 1), NLAST = 4 * SP::COLS;
       for (int i = tid; i < H6 * NPR + NLAST; i += NT) {
         int cp, row, part, col;
@@ -520,7 +511,9 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         }
         h[cp * COPY_H + row * ROW_H + part * SP::COLS + col] = (_Float16)0.0f;
       }
-      usc = __int_as_float((127 + E) << 23);
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) umx = fmaxf(umx, __shfl_xor(umx, o));
+      if ((tid & 63) == 0) wmax[tid >> 6] = umx;
     }
   }
 
@@ -572,6 +565,26 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     for (int j = 0; j < BC; ++j) acc[i][j] = 0.0f;
 
   __syncthreads();
+  if constexpr (SPLIT) {
+    if constexpr (UNF != ADJ_HALF) {
+      // the tile's scale 2^E: none (E = 0) when the largest |u| lies in [2^-4, 2^14), where the heads stay
+      // below 2^14 and the absolute resolution of the split (2^-36) is far below the FP32 rounding of the
+      // largest terms; else largest |u| / 2^E in [2^13, 2^14), and the planes are written again
+      float m = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) m = fmaxf(m, wmax[w]);
+      if (!(m >= 0.0625f && m < 16384.0f)) {
+        const int E = min(max(((__float_as_int(m) >> 23) & 0xff) - 127 - 13, -100), 100);
+        const float isc = __int_as_float((127 - E) << 23);
+        for (int idx = tid; idx < H6 * W6; idx += NT) {
+          const int r = idx / W6, c = idx - r * W6;
+          split_store<TW, TH>(u16w, r, c, u6[idx] * isc);
+        }
+        usc = __int_as_float((127 + E) << 23);
+        __syncthreads();
+      }
+    }
+  }
 
   const int nf = pb.nf;
   for (int c0 = 0; c0 < nf; c0 += NC) {

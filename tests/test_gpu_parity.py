@@ -145,3 +145,43 @@ def test_gradient_tile_configs(shape, bc, cfg):
     assert rel_inf(g, g_ora) <= 1e-4, (shape, bc, cfg, rel_inf(g, g_ora))
     assert abs(F - oracle.energy_F(x, bank, theta, oracle.COMBINED, bc)) <= 2e-6 * abs(F)
     s.close()
+
+
+@pytest.mark.parametrize("scale", [1e-5, 1e2, "targets"])
+@pytest.mark.parametrize("model", MODELS)
+def test_split_engine_tile_scaling(model, scale):
+    """Intensities outside [2^-4, 2^14), where the split-FP16 engine scales u per tile by a power of two
+    before splitting it: its gradient and F are as close to the oracle as those of the FP32-operand engine
+    (within 2x, or within the FP32 bars).  At large intensities FP32 itself loses the fine scale of y (the
+    zero-mean filters cancel to |y| ~ 1 against u ~ 1e5), so both engines are held to each other there;
+    "targets" scales 6 pixels by 200 (bright point targets), so that only their tiles are rescaled.  F
+    also gets the absolute error of FP32 log(1 + y^2): 1 + y^2 is rounded to FP32 (relative error <= 2^-24),
+    so each term theta_i log(1 + y^2) may be off by theta_i 2^-24, which dominates when every y is tiny."""
+    torch, dev = torch_dev()
+    H, W = 70, 45
+    clean, f = speckled(H, W, seed=5)
+    f = f.astype(np.float64)
+    if scale == "targets":
+        idx = np.random.default_rng(9).choice(H * W, 6, replace=False)
+        f.reshape(-1)[idx] *= 200.0
+    else:
+        f = f * scale
+    f = f.astype(np.float32)
+    bank, theta = bank_and_theta("dct", seed=3)
+    x = state_for(model, f)
+    l1, l2 = LAMS[model]
+    g_ora = oracle.grad_F(x, bank, theta, model, oracle.SYMMETRIC)
+    F_ora = oracle.energy_F(x, bank, theta, model, oracle.SYMMETRIC)
+    tol_F = 2e-6 * abs(F_ora) + 2.0 ** -24 * float(np.sum(theta)) * H * W
+    err_g, err_F = {}, {}
+    for engine in (2, 3):
+        s = make_solver(H, W, bank, theta, model=model, boundary=oracle.SYMMETRIC, lambda1=l1, lambda2=l2,
+                        engine=engine)
+        err_g[engine] = rel_inf(s.eval_gradient(_gpu(x, dev)).cpu().numpy(), g_ora)
+        F, G = s.eval_energy(_gpu(x, dev), _gpu(f, dev))
+        err_F[engine] = abs(F - F_ora)
+        s.close()
+    print(f"model {model} scale {scale}: grad err fp32 {err_g[2]:.2e} split {err_g[3]:.2e}; "
+          f"F err fp32 {err_F[2]:.2e} split {err_F[3]:.2e} (bar {tol_F:.2e})")
+    assert err_g[3] <= max(1e-4, 2.0 * err_g[2]), err_g
+    assert err_F[3] <= max(tol_F, 2.0 * err_F[2]), (err_F, tol_F)
