@@ -134,10 +134,23 @@ template <> struct ForwardOps<FWD_MFMA_F16X> {
   float sc, sclo;       // 2^E and 2^(E - 12)
 };
 
+// Row stride of the z planes (the tile + 3 halo, TW + 6 wide): the split engine pads it to a multiple of 8
+// floats, so that the adjoint's 10-wide window rows load as two 16-byte reads and a pair, and the
+// 2 x 8 position patches of its forward store z into distinct LDS banks.
+constexpr int z_row_stride(int tw, int fwd) { return fwd == FWD_MFMA_F16X ? (tw + 2 * R + 7) / 8 * 8 : tw + 2 * R; }
+// Stride of the z planes: with padded rows the plane is padded too, to 4 (mod 64) floats, so that lanes
+// that read the same position of 16 different planes (the fold) fall in 16 different banks.
+constexpr int z_plane_stride(int tw, int th, int fwd) {
+  return fwd == FWD_MFMA_F16X ? (th + 2 * R) * z_row_stride(tw, fwd) + ((4 - (th + 2 * R) * z_row_stride(tw, fwd) % 64) % 64 + 64) % 64
+                              : (th + 2 * R) * (tw + 2 * R);
+}
+
 // LDS planes of the split-FP16 engine: u6 / 2^E as FP16 heads and tails, row by row ([head row][tail
 // row], COLS halves each), in two copies: copy 0 holds column c at c, copy 1 holds column c + 1 at c,
 // so that the 8 consecutive columns of a B operand start on a 4-byte boundary in one of them.  One
 // padding row and the padding columns hold zeros: they meet the zero taps of row 7 and column 7.
+// Copy 1 starts at a word offset of 23 (mod 64): with the 2 x 8 position patches of the forward, the
+// B loads of a wave then fall in distinct banks (64 banks of 4 bytes) for either column parity.
 template <int TW, int TH>
 struct SplitPlanes {
   static constexpr int W6 = TW + 4 * R, H6 = TH + 4 * R;
@@ -145,7 +158,8 @@ struct SplitPlanes {
   static constexpr int ROWS = H6 + 1;
   static constexpr int ROW_W = COLS;             // words per plane row (head + tail)
   static constexpr int COPY_W = ROWS * ROW_W;    // words per copy
-  static constexpr int WORDS = 2 * COPY_W;
+  static constexpr int COPY1 = COPY_W + ((23 - COPY_W % 64) % 64 + 64) % 64;   // word offset of copy 1
+  static constexpr int WORDS = COPY1 + COPY_W;
   static constexpr int TAIL_W = COLS / 2;        // word offset of the tail row
 };
 
@@ -159,45 +173,34 @@ __device__ __forceinline__ void split_store(unsigned* u16w, int r, int c, float 
   q[0] = hi;
   q[SP::COLS] = lo;
   if (c > 0) {   // copy 1 holds column c at c - 1
-    q[2 * SP::COPY_W - 1] = hi;
-    q[2 * SP::COPY_W - 1 + SP::COLS] = lo;
+    q[2 * SP::COPY1 - 1] = hi;
+    q[2 * SP::COPY1 - 1 + SP::COLS] = lo;
   }
 }
 
-// One chunk of the FP32 matrix-core forward bank on the R3 region of a TW x TH tile: the position
-// groups g0, g0 + GS, ... (16 consecutive positions each, GS groups apart).  Per group, twelve
-// v_mfma_f32_16x16x4f32 take taps 0..47 (lane (m, k): A = filter m at tap 4s + k, B = u6 at tap
-// 4s + k of position m) and the VALU adds tap 48; lane (m, k) then holds y for position m, filters
-// 4k .. 4k + 3, and stores z = y / (1 + y^2) into the z planes.  Returns this thread's sum of
-// theta ln(1 + y^2) over its own (tile, in-image) positions.  ALL_IN: every R3 position lies in the
-// image, so that no z needs masking and every tile position is an own one.  FUSION == FWD_HALF also stores z of
-// the own positions to HBM (zb = plane of the chunk's first filter at the image, zstride apart).
-// Lanes past the last position compute position 0 and store its value there again: the same bits
-// as the lane that owns it, so the duplicate store is harmless.
+// One chunk of the matrix-core forward bank on the R3 region of a TW x TH tile: the position groups
+// g0, g0 + GS, ... of 16 positions each (FP32 engine: 16 consecutive positions; split engine: 2 x 8
+// patches), with the operands of ForwardOps<FWD>; lane (m, k) then holds y for position m of the
+// group, filters 4k .. 4k + 3, and stores z = y / (1 + y^2) into the z planes.  Returns this thread's
+// sum of theta ln(1 + y^2) over its own (tile, in-image) positions.  ALL_IN: every R3 position lies in
+// the image, so that no z needs masking and every tile position is an own one.  FUSION == FWD_HALF
+// also stores z of the own positions to HBM (zb = plane of the chunk's first filter at the image,
+// zstride apart).  UNIT: the tile's u was not scaled (2^E = 1).  Lanes without a position of their own
+// in a group repeat one that another lane holds, from the same operands: they store the same bits
+// again, and the position is a halo one, so it adds no energy.
 template <int TW, int TH, int NC, int GS, int FUSION, bool ALL_IN, int FWD, bool UNIT = false>
 __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsigned* u16, float* zp,
                                                     const ForwardOps<FWD>& ops, const float (&thl)[4], int g0, int lm,
                                                     int lk, int y0, int x0, int H, int W, bool periodic, float* zb,
                                                     long long zstride, int nlive) {
   using SP = SplitPlanes<TW, TH>;
-  constexpr int W6 = TW + 4 * R, W3 = TW + 2 * R, H3 = TH + 2 * R, PLANE = H3 * W3;
-  constexpr int NGROUP = (PLANE + 15) / 16;
-  constexpr int STEP = GS * 16, DR = STEP / W3, DC = STEP % W3;   // position advance per pass
+  constexpr int W6 = TW + 4 * R, W3 = TW + 2 * R, H3 = TH + 2 * R;
+  constexpr int ZW = z_row_stride(TW, FWD), PLANE = z_plane_stride(TW, TH, FWD);
   constexpr int TLAST = (KS - 1) * W6 + (KS - 1);
-  constexpr int NFULL = PLANE / 16;                               // groups with no position past the plane
-  int p = g0 * 16 + lm, r = p / W3, c = p - r * W3;
-  // split-FP16 engine: word offset of the B operands of this lane (window row r + lk, columns c ..
-  // c + 7, in the copy where they are aligned).  A pass advances the position by STEP: DR rows and DC
-  // columns, or one row more and DC - W3 columns when the column wraps; DC and W3 are even, so the
-  // column parity and with it the copy stay the same and the offset advances by a constant.
-  static_assert(DC % 2 == 0 && W3 % 2 == 0, "a pass keeps the column parity");
-  int bw = (c & 1) * SP::COPY_W + (r + lk) * SP::ROW_W + (c >> 1);
   float ef = 0.0f;
-  // one group: PARTIAL = the last group, whose lanes past the plane take position 0
-  auto group = [&](auto partial_tag) {
-    constexpr bool PARTIAL = decltype(partial_tag)::value;
-    const bool inr = !PARTIAL || p < PLANE;
-    const int rr = inr ? r : 0, cc = inr ? c : 0, zo = inr ? p : 0;
+  // one group: this lane's position (rr, cc) of the R3 region
+  auto group = [&](int rr, int cc) {
+    const int zo = rr * ZW + cc;
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (FWD == FWD_MFMA_F32) {
       const int pbase = rr * W6 + cc;
@@ -211,7 +214,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       acc[3] = fmaf(ops.klast.w, ulast, acc[3]);
     } else {
       // window row rr + lk (+ 4 in step 1), columns cc .. cc + 7 from the copy where they are aligned
-      const unsigned* b = u16 + (inr ? bw : lk * SP::ROW_W);
+      const unsigned* b = u16 + (cc & 1) * SP::COPY1 + (rr + lk) * SP::ROW_W + (cc >> 1);
       floatx4 hh = {0.0f, 0.0f, 0.0f, 0.0f}, cr = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
@@ -230,7 +233,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
     bool inimg = true;
     if constexpr (!ALL_IN) inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
     const bool live = ALL_IN || inimg || periodic;
-    const bool own = inr && inimg && (unsigned)(rr - R) < (unsigned)TH && (unsigned)(cc - R) < (unsigned)TW;
+    const bool own = inimg && (unsigned)(rr - R) < (unsigned)TH && (unsigned)(cc - R) < (unsigned)TW;
     float e = 0.0f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -242,20 +245,43 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       e = fmaf(thl[j], __builtin_amdgcn_logf(den), e);   // theta ln 2 * log2(1 + y^2)
     }
     ef += own ? e : 0.0f;
-    p += STEP;
-    c += DC;
-    r += DR;
-    const bool wrap = c >= W3;
-    if (wrap) {
-      c -= W3;
-      r += 1;
-    }
-    if constexpr (FWD == FWD_MFMA_F16X) bw += wrap ? (DR + 1) * SP::ROW_W + (DC - W3) / 2 : DR * SP::ROW_W + DC / 2;
   };
-  int g = g0;
+  if constexpr (FWD == FWD_MFMA_F32) {
+    // groups of 16 consecutive positions; lanes past the plane in the last group take position 0
+    constexpr int NGROUP = (PLANE + 15) / 16, NFULL = PLANE / 16;
+    constexpr int STEP = GS * 16, DR = STEP / W3, DC = STEP % W3;   // position advance per pass
+    int p = g0 * 16 + lm, r = p / W3, c = p - r * W3;
+    int g = g0;
 #pragma unroll 1
-  for (; g < NFULL; g += GS) group(std::false_type{});
-  if (NFULL < NGROUP && g < NGROUP) group(std::true_type{});
+    for (; g < NFULL; g += GS) {
+      group(r, c);
+      p += STEP;
+      c += DC;
+      r += DR;
+      if (c >= W3) {
+        c -= W3;
+        r += 1;
+      }
+    }
+    if (NFULL < NGROUP && g < NGROUP) group(p < PLANE ? r : 0, p < PLANE ? c : 0);
+  } else {
+    // groups of 2 x 8 positions (lane m: row m / 8, column m % 8 of the patch), patch rows of
+    // NCB patches; lanes past the last column repeat column W3 - 1 (a halo column, never an own one)
+    constexpr int NCB = (W3 + 7) / 8, NG = (H3 / 2) * NCB;
+    static_assert(H3 % 2 == 0, "patches of two rows");
+    const int dy = lm >> 3, dx = lm & 7;
+    int rp = g0 / NCB, cb = g0 - (g0 / NCB) * NCB;
+#pragma unroll 1
+    for (int g = g0; g < NG; g += GS) {
+      group(2 * rp + dy, min(cb * 8 + dx, W3 - 1));
+      cb += GS % NCB;
+      rp += GS / NCB;
+      if (cb >= NCB) {
+        cb -= NCB;
+        rp += 1;
+      }
+    }
+  }
   return ef;
 }
 
@@ -280,15 +306,16 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
 // register blocks of BR x BC outputs per thread (NT / ((TH/BR) (TW/BC)) filter groups).
 //
 // LDS layout: u6 holds u+ on the tile + 6 halo.  Each z plane holds z_j = theta_j rho'(y_j) on
-// the tile + 3 halo (R3, row stride W3), zero off the image except under the PERIODIC map; every
+// the tile + 3 halo (R3, row stride ZW), zero off the image except under the PERIODIC map; every
 // position of the planes is written in every chunk.  fpart holds the fold partials of the
 // SYMMETRIC map on tiles within 3 of the image border, accumulated over the chunks.
 template <int TW, int TH, int NC, int NT, int BR, int BC, int FWD, int UNF = FUSED>
 __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   constexpr int W6 = TW + 4 * R, H6 = TH + 4 * R;
   constexpr int W3 = TW + 2 * R, H3 = TH + 2 * R;
-  constexpr int PLANE3 = H3 * W3;
-  constexpr int PLANE = H3 * W3;                  // one z plane: the tile + 3 halo, row stride W3
+  constexpr int PLANE3 = H3 * W3;                 // positions of the tile + 3 halo
+  constexpr int ZW = z_row_stride(TW, FWD);       // z plane row stride
+  constexpr int PLANE = z_plane_stride(TW, TH, FWD);   // one z plane: the tile + 3 halo, row stride ZW
   constexpr int PPT = (PLANE3 + NT - 1) / NT;     // forward positions per thread
   constexpr int GT = (TH / BR) * (TW / BC);       // threads per adjoint group
   constexpr int NG = NT / GT;                     // filter groups
@@ -297,7 +324,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   constexpr int NPX = TH + 6;                     // layout slots per x edge
   constexpr int NSLOT = 2 * TW + 2 * NPX;          // fold layout slots
   static_assert(NT % GT == 0 && NC % NG == 0 && GT % 64 == 0 && TH % BR == 0 && TW % BC == 0, "bad tiling");
-  static_assert(BC % 2 == 0 && W3 % 2 == 0 && PLANE % 2 == 0, "adjoint reads float2 pairs");
+  static_assert(BC % 2 == 0 && ZW % 2 == 0 && PLANE % 2 == 0, "adjoint reads float2 pairs");
+  constexpr bool WIN4 = ZW % 4 == 0 && BC % 4 == 0 && PLANE % 4 == 0;   // window rows start on 16 bytes
   static_assert(NC % 8 == 0, "forward passes take 8 filters");
   static_assert(NG * TH * TW <= NC * PLANE, "epilogue does not fit in the z buffer");
   static_assert((NC & (NC - 1)) == 0 && TH >= R && TW >= R, "fold items: NC a power of two, tiles >= 3");
@@ -490,7 +518,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       // the planes were written unscaled (E = 0); the zero padding, and this wave's largest |u| for the
       // check after the barrier below
       _Float16* h = reinterpret_cast<_Float16*>(u16w);
-      constexpr int COPY_H = 2 * SP::COPY_W, ROW_H = 2 * SP::ROW_W;
+      constexpr int COPY_H = 2 * SP::COPY1, ROW_H = 2 * SP::ROW_W;
       constexpr int NP0 = SP::COLS - W6, NPR = 2 * (2 * NP0 + 1), NLAST = 4 * SP::COLS;
       for (int i = tid; i < H6 * NPR + NLAST; i += NT) {
         int cp, row, part, col;
@@ -548,7 +576,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     int gy = y0 - R + r, gx = x0 - R + c;
     bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
     fbase[k] = idx < PLANE3 ? r * W6 + c : -1;
-    zofs[k] = r * W3 + c;
+    zofs[k] = r * ZW + c;
     flive[k] = idx < PLANE3 && (inimg || bc == PERIODIC);
     fown[k] = idx < PLANE3 && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
   }
@@ -678,7 +706,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
         const bool live = inr && (inimg || bc == PERIODIC);
         const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
-        const int zo = r * W3 + c;
+        const int zo = r * ZW + c;
         // the position's u(p) is the same for the 4 filters of this lane; fetch it per lane
         float e = 0.0f;
 #pragma unroll
@@ -809,16 +837,33 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         kt[t] = q4.x; kt[t + 1] = q4.y; kt[t + 2] = q4.z; kt[t + 3] = q4.w;
       }
       const float* zplane = zp + j * PLANE;
-      const float* zb = zplane + row0 * W3 + col0;
+      const float* zb = zplane + row0 * ZW + col0;
       // stream the (BR+6) x (BC+6) window one row at a time; row q feeds output rows q - ta
 #pragma unroll
       for (int q = 0; q < WR; ++q) {
         float wrow[WC];
+        if constexpr (WIN4) {
 #pragma unroll
-        for (int s = 0; s < WC; s += 2) {
-          float2 v2 = *reinterpret_cast<const float2*>(zb + q * W3 + s);
-          wrow[s] = v2.x;
-          wrow[s + 1] = v2.y;
+          for (int s = 0; s + 4 <= WC; s += 4) {
+            const float4 v4 = *reinterpret_cast<const float4*>(zb + q * ZW + s);
+            wrow[s] = v4.x;
+            wrow[s + 1] = v4.y;
+            wrow[s + 2] = v4.z;
+            wrow[s + 3] = v4.w;
+          }
+#pragma unroll
+          for (int s = WC / 4 * 4; s < WC; s += 2) {
+            const float2 v2 = *reinterpret_cast<const float2*>(zb + q * ZW + s);
+            wrow[s] = v2.x;
+            wrow[s + 1] = v2.y;
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < WC; s += 2) {
+            const float2 v2 = *reinterpret_cast<const float2*>(zb + q * ZW + s);
+            wrow[s] = v2.x;
+            wrow[s + 1] = v2.y;
+          }
         }
 #pragma unroll
         for (int ta = 0; ta < KS; ++ta) {
@@ -843,9 +888,9 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           if (j >= ncur) continue;
           float* out = fpart + ((lo ? 0 : TW) + p0) * R * NC + j;
           if (lo)
-            fold_block<FB, NC, 1, W3, 1, KS>(zp + j * PLANE + R * W3 + p0, ka_s + j * KAP + (R + 1) * KS, out);
+            fold_block<FB, NC, 1, ZW, 1, KS>(zp + j * PLANE + R * ZW + p0, ka_s + j * KAP + (R + 1) * KS, out);
           else
-            fold_block<FB, NC, 1, -W3, 1, -KS>(zp + j * PLANE + (H - 1 - y0 + R) * W3 + p0,
+            fold_block<FB, NC, 1, -ZW, 1, -KS>(zp + j * PLANE + (H - 1 - y0 + R) * ZW + p0,
                                                ka_s + j * KAP + (R - 1) * KS, out);
         } else if (it < f_c0) {
           // x edge block, tile rows p0 .. p0 + FB - 1: z lines are plane columns, taps run down tap columns
@@ -854,9 +899,9 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           if (j >= ncur) continue;
           float* out = fpart + (2 * TW + (lo ? 0 : NPX) + p0) * R * NC + j;
           if (lo)
-            fold_block<FB, NC, W3, 1, KS, 1>(zp + j * PLANE + p0 * W3 + R, ka_s + j * KAP + R + 1, out);
+            fold_block<FB, NC, ZW, 1, KS, 1>(zp + j * PLANE + p0 * ZW + R, ka_s + j * KAP + R + 1, out);
           else
-            fold_block<FB, NC, W3, -1, KS, -1>(zp + j * PLANE + p0 * W3 + W - 1 - x0 + R, ka_s + j * KAP + R - 1,
+            fold_block<FB, NC, ZW, -1, KS, -1>(zp + j * PLANE + p0 * ZW + W - 1 - x0 + R, ka_s + j * KAP + R - 1,
                                                out);
         } else {
           // a corner row (-1 - i or H + i) of an x edge: window rows outside the plane are off the image
@@ -876,7 +921,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           float Z[R][KS], K[R][KS];
 #pragma unroll
           for (int t = 0; t < KS; ++t) {
-            const int ro = min(max(prow + t, 0), H3 - 1) * W3;
+            const int ro = min(max(prow + t, 0), H3 - 1) * ZW;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
               Z[r][t] = zpl[zc0 + ro + r * zls];
