@@ -178,6 +178,32 @@ __device__ __forceinline__ void split_store(unsigned* u16w, int r, int c, float 
   }
 }
 
+// The live and own bits (bits 2i and 2i + 1) of the passes i of lane m of wave g0 in the split engine's
+// 2 x 8 patch groups: the same in every chunk, so they are formed once per launch.
+template <int TW, int TH, int GS>
+__device__ __forceinline__ unsigned patch_masks(int g0, int lm, int y0, int x0, int H, int W, bool periodic) {
+  constexpr int W3 = TW + 2 * R, H3 = TH + 2 * R, NCB = (W3 + 7) / 8, NG = (H3 / 2) * NCB;
+  static_assert(2 * ((NG + GS - 1) / GS) <= 32, "two bits per pass");
+  const int dy = lm >> 3, dx = lm & 7;
+  int rp = g0 / NCB, cb = g0 - (g0 / NCB) * NCB;
+  unsigned m = 0u;
+  int bit = 0;
+  for (int g = g0; g < NG; g += GS, bit += 2) {
+    const int rr = 2 * rp + dy, cc = cb * 8 + dx;
+    const bool inimg = (unsigned)(y0 - R + rr) < (unsigned)H && (unsigned)(x0 - R + cc) < (unsigned)W;
+    const bool own = inimg && (unsigned)(rr - R) < (unsigned)TH && (unsigned)(cc - R) < (unsigned)TW;
+    m |= (unsigned)(inimg || periodic) << bit;
+    m |= (unsigned)own << (bit + 1);
+    cb += GS % NCB;
+    rp += GS / NCB;
+    if (cb >= NCB) {
+      cb -= NCB;
+      rp += 1;
+    }
+  }
+  return m;
+}
+
 // One chunk of the matrix-core forward bank on the R3 region of a TW x TH tile: the position groups
 // g0, g0 + GS, ... of 16 positions each (FP32 engine: 16 consecutive positions; split engine: 2 x 8
 // patches), with the operands of ForwardOps<FWD>; lane (m, k) then holds y for position m of the
@@ -192,15 +218,15 @@ template <int TW, int TH, int NC, int GS, int FUSION, bool ALL_IN, int FWD, bool
 __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsigned* u16, float* zp,
                                                     const ForwardOps<FWD>& ops, const float (&thl)[4], int g0, int lm,
                                                     int lk, int y0, int x0, int H, int W, bool periodic, float* zb,
-                                                    long long zstride, int nlive) {
+                                                    long long zstride, int nlive, unsigned pmask) {
   using SP = SplitPlanes<TW, TH>;
   constexpr int W6 = TW + 4 * R, W3 = TW + 2 * R, H3 = TH + 2 * R;
-  constexpr int ZW = z_row_stride(TW, FWD), PLANE = z_plane_stride(TW, TH, FWD);
+  constexpr int ZW = z_row_stride(TW, FWD), PLANE = z_plane_stride(TW, TH, FWD), PLANE3 = H3 * W3;
   constexpr int TLAST = (KS - 1) * W6 + (KS - 1);
   float ef = 0.0f;
-  // one group: this lane's position (rr, cc) of the R3 region
-  auto group = [&](int rr, int cc) {
-    const int zo = rr * ZW + cc;
+  // one group: this lane's position (rr, cc) of the R3 region; live: z is kept (in the image, or periodic);
+  // own: a tile position in the image, whose energy counts
+  auto group = [&](int rr, int cc, int bw, int zo, bool live, bool own) {
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (FWD == FWD_MFMA_F32) {
       const int pbase = rr * W6 + cc;
@@ -213,8 +239,9 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       acc[2] = fmaf(ops.klast.z, ulast, acc[2]);
       acc[3] = fmaf(ops.klast.w, ulast, acc[3]);
     } else {
-      // window row rr + lk (+ 4 in step 1), columns cc .. cc + 7 from the copy where they are aligned
-      const unsigned* b = u16 + (cc & 1) * SP::COPY1 + (rr + lk) * SP::ROW_W + (cc >> 1);
+      // bw: word offset of window row rr + lk, columns cc .. cc + 7, in the copy where they are aligned
+      // (+ 4 rows in step 1)
+      const unsigned* b = u16 + bw;
       floatx4 hh = {0.0f, 0.0f, 0.0f, 0.0f}, cr = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
@@ -230,10 +257,6 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       for (int j = 0; j < 4; ++j) acc[j] = UNIT ? fmaf(cr[j], 1.0f / 4096.0f, hh[j]) : fmaf(cr[j], ops.sclo, hh[j] * ops.sc);
     }
     const int gy = y0 - R + rr, gx = x0 - R + cc;
-    bool inimg = true;
-    if constexpr (!ALL_IN) inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-    const bool live = ALL_IN || inimg || periodic;
-    const bool own = inimg && (unsigned)(rr - R) < (unsigned)TH && (unsigned)(cc - R) < (unsigned)TW;
     float e = 0.0f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -248,13 +271,21 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
   };
   if constexpr (FWD == FWD_MFMA_F32) {
     // groups of 16 consecutive positions; lanes past the plane in the last group take position 0
-    constexpr int NGROUP = (PLANE + 15) / 16, NFULL = PLANE / 16;
+    constexpr int NGROUP = (PLANE3 + 15) / 16, NFULL = PLANE3 / 16;
     constexpr int STEP = GS * 16, DR = STEP / W3, DC = STEP % W3;   // position advance per pass
     int p = g0 * 16 + lm, r = p / W3, c = p - r * W3;
+    auto masks = [&](int rr, int cc, bool& live, bool& own) {
+      bool inimg = true;
+      if constexpr (!ALL_IN) inimg = (unsigned)(y0 - R + rr) < (unsigned)H && (unsigned)(x0 - R + cc) < (unsigned)W;
+      live = ALL_IN || inimg || periodic;
+      own = inimg && (unsigned)(rr - R) < (unsigned)TH && (unsigned)(cc - R) < (unsigned)TW;
+    };
     int g = g0;
 #pragma unroll 1
     for (; g < NFULL; g += GS) {
-      group(r, c);
+      bool live, own;
+      masks(r, c, live, own);
+      group(r, c, 0, r * ZW + c, live, own);
       p += STEP;
       c += DC;
       r += DR;
@@ -263,23 +294,41 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
         r += 1;
       }
     }
-    if (NFULL < NGROUP && g < NGROUP) group(p < PLANE ? r : 0, p < PLANE ? c : 0);
+    if (NFULL < NGROUP && g < NGROUP) {
+      const int rr = p < PLANE3 ? r : 0, cc = p < PLANE3 ? c : 0;
+      bool live, own;
+      masks(rr, cc, live, own);
+      group(rr, cc, 0, rr * ZW + cc, live, own);
+    }
   } else {
-    // groups of 2 x 8 positions (lane m: row m / 8, column m % 8 of the patch), patch rows of
-    // NCB patches; lanes past the last column repeat column W3 - 1 (a halo column, never an own one)
+    // groups of 2 x 8 positions (lane m: row m / 8, column m % 8 of the patch), patch rows of NCB
+    // patches.  The last patch of a row reaches past the region to column 8 NCB - 1: those positions lie
+    // in the padding columns of the z rows (never read), their windows in the zero padding of the u
+    // planes, and they are never own ones.  pmask holds the live and own bits of this lane's passes
+    // (patch_masks).  A pass advances NCB-patch rows and patches by constants, so the B offset bw and
+    // the z offset zo advance by one of two constants (the wrap is the same for the whole wave).
     constexpr int NCB = (W3 + 7) / 8, NG = (H3 / 2) * NCB;
     static_assert(H3 % 2 == 0, "patches of two rows");
+    static_assert(8 * NCB <= ZW && 8 * NCB + 6 <= SP::COLS, "the last patch stays inside the padded rows");
+    constexpr int DR = 2 * (GS / NCB), DC = 8 * (GS % NCB);          // per pass, and + 2 / - 8 NCB on a wrap
+    constexpr int DBW = DR * SP::ROW_W + DC / 2, DBW_WRAP = (DR + 2) * SP::ROW_W + (DC - 8 * NCB) / 2;
+    constexpr int DZO = DR * ZW + DC, DZO_WRAP = (DR + 2) * ZW + DC - 8 * NCB;
     const int dy = lm >> 3, dx = lm & 7;
     int rp = g0 / NCB, cb = g0 - (g0 / NCB) * NCB;
+    int rr = 2 * rp + dy, cc = cb * 8 + dx;
+    int bw = (cc & 1) * SP::COPY1 + (rr + lk) * SP::ROW_W + (cc >> 1), zo = rr * ZW + cc;
+    unsigned m = pmask;
 #pragma unroll 1
     for (int g = g0; g < NG; g += GS) {
-      group(2 * rp + dy, min(cb * 8 + dx, W3 - 1));
+      group(rr, cc, bw, zo, ALL_IN || (m & 1u), (m & 2u) != 0u);
+      m >>= 2;
       cb += GS % NCB;
-      rp += GS / NCB;
-      if (cb >= NCB) {
-        cb -= NCB;
-        rp += 1;
-      }
+      const bool wrap = cb >= NCB;
+      if (wrap) cb -= NCB;
+      rr += wrap ? DR + 2 : DR;
+      cc += wrap ? DC - 8 * NCB : DC;
+      bw += wrap ? DBW_WRAP : DBW;
+      zo += wrap ? DZO_WRAP : DZO;
     }
   }
   return ef;
@@ -614,6 +663,10 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     }
   }
 
+  // split engine: live / own bits of this lane's forward passes, the same in every chunk
+  unsigned pmask = 0u;
+  if constexpr (SPLIT) pmask = patch_masks<TW, TH, NT / 64>(tid >> 6, tid & 15, y0, x0, H, W, bc == PERIODIC);
+
   const int nf = pb.nf;
   for (int c0 = 0; c0 < nf; c0 += NC) {
     const int ncur = min(NC, nf - c0);
@@ -760,14 +813,14 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       float ef;
       if (FWD == FWD_MFMA_F16X && usc == 1.0f)
         ef = all_in ? mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, true, FWD, true>(
-                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur)
+                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur, pmask)
                     : mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, false, FWD, true>(
-                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur);
+                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur, pmask);
       else
         ef = all_in ? mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, true, FWD>(
-                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur)
+                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur, pmask)
                     : mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, false, FWD>(
-                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur);
+                          u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur, pmask);
       accF += (double)ef;
     } else {
       // ---- stage 2: forward bank on tile + 3 halo; one row of taps of 8 filters (in SGPRs) per pass
