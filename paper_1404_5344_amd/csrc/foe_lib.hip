@@ -46,10 +46,10 @@ foe_status fail(foe_status st, const std::string& msg) {
   } while (0)
 
 // Tile configurations of the fused kernel (chosen per solver, by the autotuner if asked).
-// V_NT threads per workgroup; the FP32 matrix-core engine runs V_NT_MFMA (16 waves: four per SIMD hide
-// the LDS and matrix-pipe latencies better, and its registers fit in the 128 VGPRs that allows).
+// V_NT threads per workgroup; the FP32 and split-FP16 matrix-core engines run V_NT_MFMA (16 waves: four per
+// SIMD hide the LDS and matrix-pipe latencies better, and their registers fit in the 128 VGPRs that allows).
 constexpr int V_NC = 16, V_NT = 512, V_NT_MFMA = 1024, V_BR = 4, V_BC = 2;
-// adjoint block width of the FP32 matrix-core kernels: 4 x 4 output blocks on 32 x 32 tiles
+// adjoint block width of the matrix-core kernels: 4 x 4 output blocks on 32 x 32 tiles
 constexpr int bc_mfma(int th) { return th == 32 ? 4 : V_BC; }
 struct TileCfg {
   int tw, th;

@@ -1,4 +1,6 @@
-// Fused FoE trial kernel, VALU direct-convolution engine.
+// Fused FoE trial kernel.  The forward bank runs on one of four engines: the split-FP16 matrix-core
+// engine (FP32 operands as FP16 heads and scaled tails), the FP32 matrix-core engine, the BF16
+// matrix-core engine, or the VALU direct convolution; the rest of the trial is the same code.
 //
 // One workgroup owns one TH x TW output tile and runs, entirely on chip:
 //   1. the inertial step and the pointwise prox on the tile + 6-pixel halo
