@@ -185,3 +185,39 @@ def test_split_engine_tile_scaling(model, scale):
           f"F err fp32 {err_F[2]:.2e} split {err_F[3]:.2e} (bar {tol_F:.2e})")
     assert err_g[3] <= max(1e-4, 2.0 * err_g[2]), err_g
     assert err_F[3] <= max(tol_F, 2.0 * err_F[2]), (err_F, tol_F)
+
+
+def test_auto_engine_falls_back_for_large_taps():
+    """AUTO takes the split-FP16 engine only when every abs(tap) < 2^14; a bank beyond that runs on the
+    FP32-operand engine: bitwise the same gradient and energies as asking for that engine."""
+    torch, dev = torch_dev()
+    H, W = 37, 64
+    clean, f = speckled(H, W, seed=11)
+    f = (f.astype(np.float64) * 1e-4).astype(np.float32)       # keeps y = K u of order 1
+    bank, theta = bank_and_theta("dct", seed=2)
+    bank = (np.asarray(bank, np.float64) * 6e4).astype(np.float32)
+    assert np.abs(bank).max() >= 2.0 ** 14
+    x = state_for(oracle.COMBINED, f)
+    out = {}
+    for engine in (0, 2):   # AUTO, FP32 operands
+        s = make_solver(H, W, bank, theta, engine=engine)
+        g = s.eval_gradient(_gpu(x, dev)).cpu().numpy()
+        out[engine] = (g, s.eval_energy(_gpu(x, dev), _gpu(f, dev)))
+        s.close()
+    assert np.array_equal(out[0][0], out[2][0])
+    assert out[0][1] == out[2][1]
+
+
+def test_auto_engine_is_the_split_engine():
+    """With every abs(tap) < 2^14 AUTO runs the split-FP16 engine: bitwise its gradient and energies."""
+    torch, dev = torch_dev()
+    H, W = 37, 64
+    clean, f = speckled(H, W, seed=12)
+    bank, theta = bank_and_theta("random", seed=4)
+    x = state_for(oracle.COMBINED, f)
+    out = {}
+    for engine in (0, 3):   # AUTO, split FP16
+        s = make_solver(H, W, bank, theta, engine=engine)
+        out[engine] = (s.eval_gradient(_gpu(x, dev)).cpu().numpy(), s.eval_energy(_gpu(x, dev), _gpu(f, dev)))
+        s.close()
+    assert np.array_equal(out[0][0], out[3][0]) and out[0][1] == out[3][1]
