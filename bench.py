@@ -435,6 +435,8 @@ def main():
                           "FP32 VALU)",
                 "ms_per_launch": round(ms_launch, 5), "flop_per_launch": flop,
                 "frac_mixed_peak": round(achieved / MIXED_PEAK_TFLOPS, 4),
+                "limiter": "VALU issue: the adjoint's FMAs run on the VALU without packed FP32; the forward's "
+                           "matrix-core cycles are a small share (hardware counters in profiles/)",
                 "mixed_peak_tflops": round(MIXED_PEAK_TFLOPS, 1),
                 "kernel_source_hash": kernel_source_hash()}
     s.close()
