@@ -667,7 +667,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
 
   // split engine: live / own bits of this lane's forward passes, the same in every chunk
   unsigned pmask = 0u;
-  if constexpr (SPLIT) pmask = patch_masks<TW, TH, NT / 64>(tid >> 6, tid & 15, y0, x0, H, W, bc == PERIODIC);
+  if constexpr (SPLIT)   // the wave index is uniform: the patch counters live in scalar registers
+    pmask = patch_masks<TW, TH, NT / 64>(__builtin_amdgcn_readfirstlane(tid >> 6), tid & 15, y0, x0, H, W, bc == PERIODIC);
 
   const int nf = pb.nf;
   for (int c0 = 0; c0 < nf; c0 += NC) {
@@ -714,7 +715,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       // FP32 term u(p) * sum_t k[t] is added back after the product.  Each operand is split into a BF16
       // head and a BF16 tail (x = hi + lo), and three products hi*hi + hi*lo + lo*hi are accumulated,
       // which keeps the energies of the line search at close to FP32 accuracy.
-      const int lane = tid & 63, wave = tid >> 6, lm = lane & 15, lk = lane >> 4;
+      const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lm = lane & 15, lk = lane >> 4;
       bf16x8 a16[2], a16lo[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       // k = lane / 16) holds the A value Kflip[filter m][tap 4s + k] and the B value u6 at tap 4s + k of
       // position m.  Split-FP16 engine: the operands of ForwardOps<FWD_MFMA_F16X>, staged per lane in
       // kf_s.  Either way the result lands as y for position m, filters 4k .. 4k + 3.
-      const int lane = tid & 63, wave = tid >> 6, lm = lane & 15, lk = lane >> 4;
+      const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lm = lane & 15, lk = lane >> 4;
       ForwardOps<FWD> ops;
       if constexpr (FWD == FWD_MFMA_F32) {
         constexpr int NS4 = KK / 4;                  // 12 MFMA steps of 4 taps; KK = 4 NS4 + 1
