@@ -185,15 +185,26 @@ __device__ __forceinline__ void split_store(unsigned* u16w, int r, int c, float 
 template <int TW, int TH, int GS>
 __device__ __forceinline__ unsigned patch_masks(int g0, int lm, int y0, int x0, int H, int W, bool periodic) {
   constexpr int W3 = TW + 2 * R, H3 = TH + 2 * R, NCB = (W3 + 7) / 8, NG = (H3 / 2) * NCB;
-  static_assert(2 * ((NG + GS - 1) / GS) <= 32, "two bits per pass");
+  static_assert(2 * ((NG + GS - 1) / GS) <= 32 && NCB <= 32, "two bits per pass, one per patch column");
   const int dy = lm >> 3, dx = lm & 7;
+  // column tests of the lane's NCB columns 8 cb + dx, once; the row tests of a pass take one of the two
+  // rows of its patch row, both tested in scalar registers (g0 and the patch counters are wave-uniform)
+  unsigned colin = 0u, colown = 0u;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int cc = cb * 8 + dx;
+    colin |= (unsigned)((unsigned)(x0 - R + cc) < (unsigned)W) << cb;
+    colown |= (unsigned)((unsigned)(cc - R) < (unsigned)TW) << cb;
+  }
   int rp = g0 / NCB, cb = g0 - (g0 / NCB) * NCB;
   unsigned m = 0u;
   int bit = 0;
   for (int g = g0; g < NG; g += GS, bit += 2) {
-    const int rr = 2 * rp + dy, cc = cb * 8 + dx;
-    const bool inimg = (unsigned)(y0 - R + rr) < (unsigned)H && (unsigned)(x0 - R + cc) < (unsigned)W;
-    const bool own = inimg && (unsigned)(rr - R) < (unsigned)TH && (unsigned)(cc - R) < (unsigned)TW;
+    const int r0 = 2 * rp;
+    const bool rin0 = (unsigned)(y0 - R + r0) < (unsigned)H, rin1 = (unsigned)(y0 - R + r0 + 1) < (unsigned)H;
+    const bool rown0 = (unsigned)(r0 - R) < (unsigned)TH, rown1 = (unsigned)(r0 + 1 - R) < (unsigned)TH;
+    const bool inimg = (dy ? rin1 : rin0) && ((colin >> cb) & 1u);
+    const bool own = inimg && (dy ? rown1 : rown0) && ((colown >> cb) & 1u);
     m |= (unsigned)(inimg || periodic) << bit;
     m |= (unsigned)own << (bit + 1);
     cb += GS % NCB;
