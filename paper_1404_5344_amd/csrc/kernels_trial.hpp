@@ -239,7 +239,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
   float ef = 0.0f;
   // one group: this lane's position (rr, cc) of the R3 region; live: z is kept (in the image, or periodic);
   // own: a tile position in the image, whose energy counts
-  auto group = [&](int rr, int cc, int bw, int zo, bool live, bool own) {
+  auto group = [&](int rr, int cc, const unsigned* b, float* zq, bool live, bool own) {
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (FWD == FWD_MFMA_F32) {
       const int pbase = rr * W6 + cc;
@@ -252,9 +252,8 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       acc[2] = fmaf(ops.klast.z, ulast, acc[2]);
       acc[3] = fmaf(ops.klast.w, ulast, acc[3]);
     } else {
-      // bw: word offset of window row rr + lk, columns cc .. cc + 7, in the copy where they are aligned
-      // (+ 4 rows in step 1)
-      const unsigned* b = u16 + bw;
+      // b: window row rr + lk, columns cc .. cc + 7, in the copy where they are aligned (+ 4 rows in
+      // step 1)
       floatx4 hh = {0.0f, 0.0f, 0.0f, 0.0f}, cr = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
@@ -276,7 +275,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       const float yv = acc[j];
       const float den = fmaf(yv, yv, 1.0f);
       const float z = yv * fast_rcp(den);
-      zp[(4 * lk + j) * PLANE + zo] = live ? z : 0.0f;
+      zq[(4 * lk + j) * PLANE] = live ? z : 0.0f;   // zq: this position in plane 0
       if (FUSION == FWD_HALF && own && 4 * lk + j < nlive) zb[(4 * lk + j) * zstride + (long long)gy * W + gx] = z;
       e = fmaf(thl[j], __builtin_amdgcn_logf(den), e);   // theta ln 2 * log2(1 + y^2)
     }
@@ -298,7 +297,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
     for (; g < NFULL; g += GS) {
       bool live, own;
       masks(r, c, live, own);
-      group(r, c, 0, r * ZW + c, live, own);
+      group(r, c, u16, zp + r * ZW + c, live, own);
       p += STEP;
       c += DC;
       r += DR;
@@ -311,15 +310,15 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       const int rr = p < PLANE3 ? r : 0, cc = p < PLANE3 ? c : 0;
       bool live, own;
       masks(rr, cc, live, own);
-      group(rr, cc, 0, rr * ZW + cc, live, own);
+      group(rr, cc, u16, zp + rr * ZW + cc, live, own);
     }
   } else {
     // groups of 2 x 8 positions (lane m: row m / 8, column m % 8 of the patch), patch rows of NCB
     // patches.  The last patch of a row reaches past the region to column 8 NCB - 1: those positions lie
     // in the padding columns of the z rows (never read), their windows in the zero padding of the u
     // planes, and they are never own ones.  pmask holds the live and own bits of this lane's passes
-    // (patch_masks).  A pass advances NCB-patch rows and patches by constants, so the B offset bw and
-    // the z offset zo advance by one of two constants (the wrap is the same for the whole wave).
+    // (patch_masks).  A pass advances NCB-patch rows and patches by constants, so the B address b and
+    // the z address zq advance by one of two constants (the wrap is the same for the whole wave).
     constexpr int NCB = (W3 + 7) / 8, NG = (H3 / 2) * NCB;
     static_assert(H3 % 2 == 0, "patches of two rows");
     static_assert(8 * NCB <= ZW && 8 * NCB + 6 <= SP::COLS, "the last patch stays inside the padded rows");
@@ -329,19 +328,20 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
     const int dy = lm >> 3, dx = lm & 7;
     int rp = g0 / NCB, cb = g0 - (g0 / NCB) * NCB;
     int rr = 2 * rp + dy, cc = cb * 8 + dx;
-    int bw = (cc & 1) * SP::COPY1 + (rr + lk) * SP::ROW_W + (cc >> 1), zo = rr * ZW + cc;
+    const unsigned* b = u16 + (cc & 1) * SP::COPY1 + (rr + lk) * SP::ROW_W + (cc >> 1);
+    float* zq = zp + rr * ZW + cc;
     unsigned m = pmask;
 #pragma unroll 1
     for (int g = g0; g < NG; g += GS) {
-      group(rr, cc, bw, zo, ALL_IN || (m & 1u), (m & 2u) != 0u);
+      group(rr, cc, b, zq, ALL_IN || (m & 1u), (m & 2u) != 0u);
       m >>= 2;
       cb += GS % NCB;
       const bool wrap = cb >= NCB;
       if (wrap) cb -= NCB;
       rr += wrap ? DR + 2 : DR;
       cc += wrap ? DC - 8 * NCB : DC;
-      bw += wrap ? DBW_WRAP : DBW;
-      zo += wrap ? DZO_WRAP : DZO;
+      b += wrap ? DBW_WRAP : DBW;
+      zq += wrap ? DZO_WRAP : DZO;
     }
   }
   return ef;
