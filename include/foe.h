@@ -178,6 +178,23 @@ foe_status foe_batch_solve(foe_solver* s, const float* d_f, const float* d_init,
 foe_status foe_autotune(foe_solver* s, const float* d_f, int32_t reps, int32_t* chosen);
 foe_status foe_set_tile_config(foe_solver* s, int32_t cfg);
 
+/* ---- Allocation-free solve, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The same solve as foe_create +
+ * foe_solve + foe_destroy (same kernels, same launch order, same bits as foe_solve on the default 32 x 32
+ * tiles), with every device buffer of the solver (x and gradient rings, tile list, partial sums, state,
+ * stats, tap tables) placed in one static device workspace of 24 MiB that the library holds on each GPU it
+ * runs on until the process ends; f is read in place.  No hipMalloc, hipFree or other allocating routine is
+ * called; kernels are launched directly (no graphs).  Arguments as foe_create (p, filters_host,
+ * weights_host, hip_stream) and foe_solve (d_f, d_init, d_u_out, sum_host, stats_host [max_iters][8]).
+ * Run it with the device of hip_stream current.  Every call on a GPU shares that GPU's workspace: calls that
+ * overlap on one GPU (two host threads, or two streams) race and must not be issued.  Nothing in the
+ * workspace needs clearing between calls: each call writes every buffer before reading it.
+ * Errors: EINVAL (parameters, UNFUSED fusion, or an image / max_iters whose buffers exceed the workspace:
+ * about 1.2 M pixels at 300 iterations), EDEVICE, and the solve statuses of foe_solve. */
+foe_status foe_solve_noalloc(const foe_params* p, const float* filters_host, const float* weights_host,
+                             void* hip_stream, const float* d_f, const float* d_init, float* d_u_out,
+                             foe_summary* sum_host, double* stats_host);
+
 /* Probes running the same kernels as the solve path. */
 /* d_grad = grad F(d_x). */
 foe_status foe_eval_gradient(foe_solver* s, const float* d_x, float* d_grad);

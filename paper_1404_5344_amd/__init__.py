@@ -78,6 +78,7 @@ def _load():
     L.foe_batch_solve.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(Summary), _DP]
     L.foe_autotune.argtypes = [_VP, _VP, ctypes.c_int32, _IP]
     L.foe_set_tile_config.argtypes = [_VP, ctypes.c_int32]
+    L.foe_solve_noalloc.argtypes = [ctypes.POINTER(Params), _VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Summary), _DP]
     L.foe_cnn_num_params.restype = ctypes.c_int64
     L.foe_cnn_create.argtypes = [_VP, _VP, ctypes.POINTER(_VP)]
     L.foe_cnn_destroy.argtypes = [_VP]
@@ -95,7 +96,7 @@ def _load():
     L.foe_abi_version.restype = ctypes.c_int32
     for name in ("foe_create", "foe_destroy", "foe_solve", "foe_solve_from", "foe_eval_gradient", "foe_eval_energy",
                  "foe_eval_prox", "foe_step", "foe_last_timing", "foe_profile_trial", "foe_batch_create",
-                 "foe_batch_layout", "foe_batch_solve", "foe_autotune", "foe_set_tile_config", "foe_cnn_create",
+                 "foe_batch_layout", "foe_batch_solve", "foe_autotune", "foe_solve_noalloc", "foe_set_tile_config", "foe_cnn_create",
                  "foe_cnn_destroy", "foe_cnn_get_params", "foe_cnn_infer", "foe_cnn_loss_grad", "foe_cnn_train_step"):
         getattr(L, name).restype = ctypes.c_int
     if L.foe_abi_version() != ABI_VERSION:
@@ -269,6 +270,32 @@ class Solver:
         n = ctypes.c_int32()
         _check(lib.foe_last_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def solve_noalloc(params: Params, filters, weights, f, init=None, out=None, stream=None,
+                  allow_failure=False) -> SolveResult:
+    """One solve through the allocation-free entry point (see foe_solve_noalloc): no solver handle, the
+    library's static device workspace in place of per-solver buffers.  out (optional) receives u."""
+    torch = _torch()
+    shape = (params.height, params.width)
+    k = np.ascontiguousarray(np.asarray(filters, dtype=np.float32).reshape(-1, 7, 7))
+    th = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).reshape(-1))
+    if k.shape[0] != params.num_filters or th.shape[0] != params.num_filters:
+        raise ValueError("filters/weights do not match num_filters")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    elif stream != torch.cuda.current_stream():
+        stream.wait_stream(torch.cuda.current_stream())
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=f.device)
+    s = Summary()
+    stats = np.zeros((max(params.max_iters, 1), STATS_COLS))
+    st = lib.foe_solve_noalloc(ctypes.byref(params), k.ctypes.data_as(_VP), th.ctypes.data_as(_VP),
+                               _VP(stream.cuda_stream), _dev_ptr(f, shape, "f"),
+                               _dev_ptr(init, shape, "init") if init is not None else None,
+                               _dev_ptr(out, shape, "out"), ctypes.byref(s), stats.ctypes.data_as(_DP))
+    _check(st, (OK, ELINESEARCH, ENONFINITE) if allow_failure else (OK,))
+    return SolveResult(out, s.as_dict(), stats[:s.iters_done].copy(), st)
 
 
 class BatchSolver(Solver):

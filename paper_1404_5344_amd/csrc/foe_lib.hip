@@ -17,6 +17,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -80,10 +82,9 @@ constexpr float SPLIT_MAX_TAP = 16384.0f;
 // The split-FP16 operands of the forward taps kf ([chunk][t][j], t = 7 a + b): per chunk and lane
 // (m = lane % 16, k = lane / 16), for steps s = 0, 1, the heads then the 4096-scaled tails of tap
 // row 4s + k, columns 0..7, of filter m (zero outside the 7 x 7 taps), two FP16 per word, the lower
-// column in the low half.
-std::vector<unsigned> split_taps(const std::vector<float>& kf) {
+// column in the low half.  out: (MAX_NF / V_NC) * F16_OPS words.
+void split_taps(const float* kf, unsigned* out) {
   const int nchunks = MAX_NF / V_NC;
-  std::vector<unsigned> out((size_t)nchunks * F16_OPS, 0u);
   for (int c = 0; c < nchunks; ++c)
     for (int lane = 0; lane < 64; ++lane) {
       const int m = lane % 16, k = lane / 16;
@@ -101,7 +102,29 @@ std::vector<unsigned> split_taps(const std::vector<float>& kf) {
             out[(size_t)c * F16_OPS + lane * 16 + s * 8 + part * 4 + i / 2] = (unsigned)hv[0] | ((unsigned)hv[1] << 16);
           }
     }
-  return out;
+}
+
+// Host copies of every tap table the kernels read, built from the caller's bank (no heap use).
+struct TapTables {
+  float kf[MAX_NF * KK];                    // forward taps, flipped and chunk-transposed
+  float ka[MAX_NF * KK];                    // adjoint taps 2 theta_i k_i
+  float theta[MAX_NF];
+  unsigned kf16[(MAX_NF / V_NC) * F16_OPS];  // split-FP16 forward operands
+};
+
+void build_tap_tables(int nf, const float* filters_host, const float* weights_host, TapTables* t) {
+  std::memset(t, 0, sizeof(TapTables));
+  for (int i = 0; i < nf; ++i) {
+    t->theta[i] = weights_host[i];
+    for (int a = 0; a < KS; ++a)
+      for (int b = 0; b < KS; ++b) {
+        const float k = filters_host[(size_t)i * KK + a * KS + b];
+        t->ka[i * KK + a * KS + b] = (float)(2.0 * (double)t->theta[i] * (double)k);   // z planes hold y/(1+y^2)
+        const int c = i / V_NC, j = i % V_NC, tt = (KS - 1 - a) * KS + (KS - 1 - b);
+        t->kf[((size_t)c * KK + tt) * V_NC + j] = k;
+      }
+  }
+  split_taps(t->kf, t->kf16);
 }
 
 }  // namespace
@@ -550,22 +573,16 @@ foe_status create_common(const foe_params* p, int n_img, const int32_t* H, const
     destroy_all(s);
     return fail(FOE_ENOMEM, "device allocation failed (" + alloc_err + ")");
   }
-  std::vector<float> kf(MAX_NF * KK, 0.0f), ka(MAX_NF * KK, 0.0f), th(MAX_NF, 0.0f);
-  for (int i = 0; i < p->num_filters; ++i) {
-    th[i] = weights_host[i];
-    for (int a = 0; a < KS; ++a)
-      for (int b = 0; b < KS; ++b) {
-        float k = filters_host[(size_t)i * KK + a * KS + b];
-        ka[i * KK + a * KS + b] = (float)(2.0 * (double)th[i] * (double)k);   // 2 theta_i k_i: z planes hold y/(1+y^2)
-        const int c = i / V_NC, j = i % V_NC, t = (KS - 1 - a) * KS + (KS - 1 - b);
-        kf[((size_t)c * KK + t) * V_NC + j] = k;
-      }
+  std::unique_ptr<TapTables> tabs(new (std::nothrow) TapTables);
+  if (!tabs) {
+    destroy_all(s);
+    return fail(FOE_ENOMEM, "host allocation failed");
   }
-  const std::vector<unsigned> kf16 = split_taps(kf);
-  hipError_t e = hipMemcpy(s->kf, kf.data(), sizeof(float) * kf.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(s->kf16, kf16.data(), sizeof(unsigned) * kf16.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(s->ka, ka.data(), sizeof(float) * ka.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(s->theta, th.data(), sizeof(float) * th.size(), hipMemcpyHostToDevice);
+  build_tap_tables(p->num_filters, filters_host, weights_host, tabs.get());
+  hipError_t e = hipMemcpy(s->kf, tabs->kf, sizeof(tabs->kf), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->kf16, tabs->kf16, sizeof(tabs->kf16), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->ka, tabs->ka, sizeof(tabs->ka), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->theta, tabs->theta, sizeof(tabs->theta), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreate(&s->ev0);
   if (e == hipSuccess) e = hipEventCreate(&s->ev1);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
@@ -900,6 +917,214 @@ foe_status foe_set_tile_config(foe_solver* s, int32_t cfg) {
   drop_graphs(s);
   build_tiles(s, cfg);
   return upload_tiles(s);
+}
+
+}  // extern "C"
+
+// ---- The allocation-free solve.  Its device workspace is one file-scope array that every call on a GPU
+// shares; each GPU holds its own copy (at its own address, found once per device with
+// hipGetSymbolAddress).  The name of the array is a host-side stand-in: host code uses only the address.
+namespace {
+
+constexpr size_t NOALLOC_BYTES = (size_t)24 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+__device__ __align__(256) unsigned char noalloc_scratch[NOALLOC_BYTES];
+void* g_noalloc_base[NOALLOC_MAX_DEVICES] = {};
+std::mutex g_noalloc_mu;
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Byte offsets of the buffers of a one-image solve inside the workspace (32 x 32 tiles).
+struct NoallocLayout {
+  size_t xr[3], gr[2], partials, partials2, stats, st, st2, images, tiles, kf, ka, kf16, theta, total;
+};
+
+NoallocLayout noalloc_layout(size_t n, int ntiles, int stats_rows) {
+  NoallocLayout l{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += align256(bytes); return at; };
+  for (auto& x : l.xr) x = take(sizeof(float) * n);
+  for (auto& g : l.gr) g = take(sizeof(float) * n);
+  l.partials = take(sizeof(double) * PART_COLS * (size_t)ntiles);
+  l.partials2 = take(sizeof(double) * PART_COLS * (size_t)ntiles);
+  l.stats = take(sizeof(double) * STAT_COLS * (size_t)stats_rows);
+  l.st = take(sizeof(DevState));
+  l.st2 = take(sizeof(DevState));
+  l.images = take(sizeof(ImageDesc));
+  l.tiles = take(sizeof(TileDesc) * (size_t)ntiles);
+  l.kf = take(sizeof(float) * MAX_NF * KK);
+  l.ka = take(sizeof(float) * MAX_NF * KK);
+  l.kf16 = take(sizeof(unsigned) * (MAX_NF / V_NC) * F16_OPS);
+  l.theta = take(sizeof(float) * MAX_NF);
+  l.total = o;
+  return l;
+}
+
+// The workspace address on the current device, looked up on the first call there.
+foe_status noalloc_base(void** out) {
+  int dev = -1;
+  HIP_OR(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(FOE_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_base[dev]) {
+    void* ptr = nullptr;
+    HIP_OR(hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch)));
+    if (!ptr) return fail(FOE_EDEVICE, "hipGetSymbolAddress returned NULL for the workspace");
+    g_noalloc_base[dev] = ptr;
+  }
+  *out = g_noalloc_base[dev];
+  return FOE_OK;
+}
+
+// The iteration loop of run_loop for one image with direct launches in place of the graphs: the same
+// kernels with the same arguments in the same order, so the results are the same bits.  Host state lives in
+// s->st_host (caller memory); nothing is allocated.
+foe_status run_loop_direct(foe_solver* s, int iters, foe_summary* sum, double* stats_host) {
+  const double L0 = s->p.L0;
+  reset_states(s, &L0, iters);
+  foe_status e = push_states(s);
+  if (e != FOE_OK) return e;
+  launch_fused(s, fused_args(s, MODE_EVAL, s->fbuf, s->xr[0], s->gr[0]), s->stream);
+  launch_decide(s, DECIDE_INIT, s->stream);
+  HIP_OR(hipGetLastError());
+  e = pull_states(s);
+  if (e != FOE_OK) return e;
+  const double G0 = s->st_host[0].sums[1];
+  for (;;) {
+    const DevState& h = s->st_host[0];
+    const int remaining = h.done ? 0 : h.target - h.iter;
+    if (remaining <= 0) break;
+    int q = 0;
+    for (int k = 0; k < remaining; ++k) {
+      FusedArgs a = fused_args(s, MODE_TRIAL, s->fbuf, nullptr, nullptr);
+      a.decide_prev = 1;
+      a.st = q ? s->st2 : s->st;
+      a.st_out = q ? s->st : s->st2;
+      a.part_in = q ? s->partials2 : s->partials;
+      a.partials = q ? s->partials : s->partials2;
+      launch_fused(s, a, s->stream);
+      q ^= 1;
+    }
+    launch_decide(s, DECIDE_STEP, s->stream, q);
+    if (q) HIP_OR(hipMemcpyAsync(s->st, s->st2, sizeof(DevState), hipMemcpyDeviceToDevice, s->stream));
+    HIP_OR(hipGetLastError());
+    e = pull_states(s);
+    if (e != FOE_OK) return e;
+  }
+  const DevState& h = s->st_host[0];
+  double last[STAT_COLS] = {};
+  if (h.iter > 0) {
+    if (stats_host) {
+      HIP_OR(hipMemcpy(stats_host, s->stats, sizeof(double) * STAT_COLS * h.iter, hipMemcpyDeviceToHost));
+      std::memcpy(last, stats_host + (size_t)(h.iter - 1) * STAT_COLS, sizeof(last));
+    } else {
+      HIP_OR(hipMemcpy(last, s->stats + (size_t)(h.iter - 1) * STAT_COLS, sizeof(last), hipMemcpyDeviceToHost));
+    }
+  }
+  if (sum) {
+    sum->iters_done = h.iter;
+    sum->total_trials = h.total_trials;
+    sum->F = h.Fcur;
+    sum->G = h.iter > 0 ? last[1] : G0;
+    sum->alpha = h.iter > 0 ? last[3] : h.alpha;
+    sum->H = sum->F + sum->G;
+    sum->L = h.L_acc;
+  }
+  return h.status != ST_OK ? status_of(h.status) : FOE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+foe_status foe_solve_noalloc(const foe_params* p, const float* filters_host, const float* weights_host,
+                             void* hip_stream, const float* d_f, const float* d_init, float* d_u_out,
+                             foe_summary* sum_host, double* stats_host) {
+  if (!p || !d_f || !d_u_out) return fail(FOE_EINVAL, "NULL argument");
+  Problem pb;
+  foe_status v = validate(p, filters_host, weights_host, &pb);
+  if (v != FOE_OK) return v;
+  if (p->fusion != FOE_FUSED) return fail(FOE_EINVAL, "the allocation-free solve runs the fused kernel only");
+  ImageDesc im{};
+  v = image_desc(p, p->height, p->width, p->lambda1, p->lambda2, p->looks, &im);
+  if (v != FOE_OK) return v;
+  const TileCfg tc = TILE_CFGS[0];
+  const int ntx = (p->width + tc.tw - 1) / tc.tw, nty = (p->height + tc.th - 1) / tc.th;
+  const size_t n = (size_t)p->height * p->width;
+  const int stats_rows = p->max_iters > 0 ? p->max_iters : 1;
+  if ((int64_t)ntx * nty > (int64_t)1 << 24) return fail(FOE_EINVAL, "image too large for the allocation-free solve");
+  const int ntiles = ntx * nty;
+  const NoallocLayout l = noalloc_layout(n, ntiles, stats_rows);
+  if (l.total > NOALLOC_BYTES)
+    return fail(FOE_EINVAL, "the allocation-free solve holds " + std::to_string(NOALLOC_BYTES) +
+                                " bytes of device workspace; this image and max_iters need " + std::to_string(l.total));
+  im.off = 0;
+  im.tile0 = 0;
+  im.ntiles = ntiles;
+  void* base = nullptr;
+  v = noalloc_base(&base);
+  if (v != FOE_OK) return v;
+  unsigned char* b = static_cast<unsigned char*>(base);
+
+  foe_solver s;   // its containers stay empty: nothing here allocates
+  DevState st_host{};
+  TapTables tabs;
+  s.p = *p;
+  s.pb = pb;
+  s.stream = (hipStream_t)hip_stream;
+  s.n_img = 1;
+  s.n = n;
+  s.tile_cfg = 0;
+  s.nblocks = ntiles;
+  s.max_tiles = ntiles;
+  for (int i = 0; i < 3; ++i) s.xr[i] = reinterpret_cast<float*>(b + l.xr[i]);
+  for (int i = 0; i < 2; ++i) s.gr[i] = reinterpret_cast<float*>(b + l.gr[i]);
+  s.fbuf = const_cast<float*>(d_f);   // f is only read
+  s.partials = reinterpret_cast<double*>(b + l.partials);
+  s.partials2 = reinterpret_cast<double*>(b + l.partials2);
+  s.stats = reinterpret_cast<double*>(b + l.stats);
+  s.stats_rows = stats_rows;
+  s.st = reinterpret_cast<DevState*>(b + l.st);
+  s.st2 = reinterpret_cast<DevState*>(b + l.st2);
+  s.st_host = &st_host;
+  s.d_images = reinterpret_cast<ImageDesc*>(b + l.images);
+  s.d_tiles = reinterpret_cast<TileDesc*>(b + l.tiles);
+  s.kf = reinterpret_cast<float*>(b + l.kf);
+  s.ka = reinterpret_cast<float*>(b + l.ka);
+  s.kf16 = reinterpret_cast<unsigned*>(b + l.kf16);
+  s.theta = reinterpret_cast<float*>(b + l.theta);
+
+  build_tap_tables(p->num_filters, filters_host, weights_host, &tabs);
+  HIP_OR(hipMemcpyAsync(s.kf, tabs.kf, sizeof(tabs.kf), hipMemcpyHostToDevice, s.stream));
+  HIP_OR(hipMemcpyAsync(s.ka, tabs.ka, sizeof(tabs.ka), hipMemcpyHostToDevice, s.stream));
+  HIP_OR(hipMemcpyAsync(s.kf16, tabs.kf16, sizeof(tabs.kf16), hipMemcpyHostToDevice, s.stream));
+  HIP_OR(hipMemcpyAsync(s.theta, tabs.theta, sizeof(tabs.theta), hipMemcpyHostToDevice, s.stream));
+  HIP_OR(hipMemcpyAsync(s.d_images, &im, sizeof(ImageDesc), hipMemcpyHostToDevice, s.stream));
+  tile_list_kernel<<<(ntiles + 255) / 256, 256, 0, s.stream>>>(s.d_tiles, ntx, ntiles, tc.tw, tc.th);
+  HIP_OR(hipGetLastError());
+
+  // a1: x^0 = x^-1 from f (or d_init), with the input check
+  reset_states(&s, &s.p.L0, s.p.max_iters);
+  foe_status e = push_states(&s);
+  if (e != FOE_OK) return e;
+  const size_t blocks = std::min<size_t>(std::max<size_t>((n + 255) / 256, 1), 1024);
+  init_state_kernel<<<dim3((unsigned)blocks, 1, 1), 256, 0, s.stream>>>(s.fbuf, d_init, s.xr[0], s.xr[1], s.d_images,
+                                                                        s.pb.model, s.st);
+  HIP_OR(hipGetLastError());
+  e = pull_states(&s);
+  if (e != FOE_OK) return e;
+  foe_status st;
+  if (st_host.input_bad) {
+    st = fail(FOE_EINPUT, "f or the initial image has a non-finite or non-positive pixel");
+    if (sum_host) std::memset(sum_host, 0, sizeof(foe_summary));
+  } else {
+    st = run_loop_direct(&s, s.p.max_iters, sum_host, stats_host);
+  }
+  finalize_kernel<<<dim3((unsigned)blocks, 1, 1), 256, 0, s.stream>>>(s.st, s.xr[0], s.xr[1], s.xr[2], d_u_out,
+                                                                      s.d_images, s.pb.model);
+  HIP_OR(hipGetLastError());
+  HIP_OR(hipStreamSynchronize(s.stream));
+  return st;
 }
 
 const char* foe_status_str(foe_status st) {

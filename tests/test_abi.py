@@ -58,3 +58,20 @@ def test_host_only_calls():
     p.engine = 4
     st = foe.lib.foe_create(ctypes.byref(p), k, th, None, ctypes.byref(h))
     assert st == foe.EINVAL and b"bad engine" in foe.lib.foe_last_error()
+
+
+def test_noalloc_rejects_oversized_images_before_any_device_call():
+    import paper_1404_5344_amd as foe
+    k = (ctypes.c_float * (48 * 49))()
+    th = (ctypes.c_float * 48)()
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: the size check comes first
+    # 2048 x 2048 needs 5 planes of 16 MiB: beyond the 24 MiB workspace
+    p = foe.default_params(2048, 2048)
+    st = foe.lib.foe_solve_noalloc(ctypes.byref(p), k, th, None, dummy, None, dummy, None, None)
+    assert st == foe.EINVAL and b"workspace" in foe.lib.foe_last_error()
+    # so do the unfused path and NULL images
+    p = foe.default_params(64, 64, fusion=1)
+    st = foe.lib.foe_solve_noalloc(ctypes.byref(p), k, th, None, dummy, None, dummy, None, None)
+    assert st == foe.EINVAL and b"fused" in foe.lib.foe_last_error()
+    p = foe.default_params(64, 64)
+    assert foe.lib.foe_solve_noalloc(ctypes.byref(p), k, th, None, None, None, dummy, None, None) == foe.EINVAL
