@@ -170,7 +170,7 @@ def form_bf16(dev):
     x0 = torch.log(f)
     res = {}
     solvers = {}
-    for name, kw in (("fp32", {}), ("bf16", dict(precision=1, engine=2))):
+    for name, kw in (("fp32", {}), ("bf16", dict(precision=1))):
         p = foe.default_params(2048, 2048, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=300, **kw)
         solvers[name] = foe.Solver(p, bank, theta)
         res[name] = _probe(solvers[name], f, x0, clean, pr.peak, 300)

@@ -110,7 +110,24 @@ struct TapTables {
   float ka[MAX_NF * KK];                    // adjoint taps 2 theta_i k_i
   float theta[MAX_NF];
   unsigned kf16[(MAX_NF / V_NC) * F16_OPS];  // split-FP16 forward operands
+  unsigned kb16[MAX_NF * KB16_W];            // BF16 adjoint operands of the BF16 engine's matrix-core adjoint
 };
+
+// The BF16 adjoint operands of filter i (ZStrips, KB16_W): T[22 a + b] = ka_i[a][b] (b < 7), zero elsewhere,
+// rounded to BF16; copy c holds T[x + c - 16] at half x, two halves per word, the lower index in the low half.
+void adjoint_operands_bf16(const float* ka_i, unsigned* out) {
+  constexpr int TW_ = 22, NH = 2 * KB16_COPY;
+  for (int copy = 0; copy < 2; ++copy)
+    for (int x = 0; x < NH; x += 2) {
+      unsigned short hv[2];
+      for (int q = 0; q < 2; ++q) {
+        const int k = x + q + copy - 16;
+        const float v = k >= 0 && k < KS * TW_ && k % TW_ < KS ? ka_i[(k / TW_) * KS + k % TW_] : 0.0f;
+        hv[q] = __builtin_bit_cast(unsigned short, (__bf16)v);
+      }
+      out[copy * KB16_COPY + x / 2] = (unsigned)hv[0] | ((unsigned)hv[1] << 16);
+    }
+}
 
 void build_tap_tables(int nf, const float* filters_host, const float* weights_host, TapTables* t) {
   std::memset(t, 0, sizeof(TapTables));
@@ -125,6 +142,7 @@ void build_tap_tables(int nf, const float* filters_host, const float* weights_ho
       }
   }
   split_taps(t->kf, t->kf16);
+  for (int i = 0; i < nf; ++i) adjoint_operands_bf16(t->ka + i * KK, t->kb16 + (size_t)i * KB16_W);
 }
 
 }  // namespace
@@ -153,6 +171,7 @@ struct foe_solver {
   float* kf = nullptr;
   float* ka = nullptr;
   unsigned* kf16 = nullptr;  // split-FP16 forward operands (FP16 pairs), F16_OPS words per chunk
+  unsigned* kb16 = nullptr;  // BF16 adjoint operands, KB16_W words per filter
   float* theta = nullptr;
   double* partials = nullptr;   // per-block partials; partials2 / st2: the other parity of the graph launches
   double* partials2 = nullptr;
@@ -211,6 +230,7 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
   a.kf = s->kf;
   a.ka = s->ka;
   a.kf16 = s->kf16;
+  a.kb16 = s->kb16;
   a.theta = s->theta;
   a.zbuf = s->zbuf;
   a.zstride = (long long)s->n;
@@ -221,7 +241,7 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
 template <int TW, int TH, int UNF>
 void launch_engine(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
   if (s->pb.engine == FWD_MFMA_BF16)
-    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_MFMA_BF16, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
+    foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_BF16, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
   else if (s->pb.engine == FWD_MFMA_F32)
     foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_F32, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
   else if (s->pb.engine == FWD_MFMA_F16X)
@@ -235,9 +255,11 @@ template <int TW, int TH>
 void launch_cfg(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
   if (s->zbuf) {
     launch_engine<TW, TH, FWD_HALF>(s, a, stream);
-    // the adjoint half runs no forward bank; it takes the thread count of the engine's fused kernel,
-    // so that both paths sum the adjoint over the filter groups in the same order
-    if (s->pb.engine == FWD_MFMA_F32 || s->pb.engine == FWD_MFMA_F16X)
+    // the adjoint half runs no forward bank; it takes the adjoint form and thread count of the engine's fused
+    // kernel, so that both paths compute the adjoint with the same arithmetic in the same order
+    if (s->pb.engine == FWD_MFMA_BF16)
+      foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_BF16, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
+    else if (s->pb.engine == FWD_MFMA_F32 || s->pb.engine == FWD_MFMA_F16X)
       foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
     else
       foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT, 0, stream>>>(a);
@@ -284,8 +306,8 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
   if (p->prox_method != FOE_PROX_NEWTON && p->prox_method != FOE_PROX_LAMBERTW) return fail(FOE_EINVAL, "bad prox_method");
   if (p->prox_method == FOE_PROX_LAMBERTW && p->model != FOE_MODEL_LOG)
     return fail(FOE_EINVAL, "the Lambert-W prox exists for the LOG model only");
-  if (p->precision == FOE_PREC_BF16 && (p->engine == FOE_ENGINE_VALU || p->engine == FOE_ENGINE_MFMA_SPLIT))
-    return fail(FOE_EINVAL, "BF16 precision runs on the MFMA engine");
+  if (p->precision == FOE_PREC_BF16 && p->engine != FOE_ENGINE_AUTO)
+    return fail(FOE_EINVAL, "BF16 precision runs its own engine (engine must be AUTO)");
   if (p->step_mode != FOE_STEP_BACKTRACK && p->step_mode != FOE_STEP_FIXED) return fail(FOE_EINVAL, "bad step_mode");
   if (p->max_iters < 0) return fail(FOE_EINVAL, "max_iters must be >= 0");
   if (p->max_backtracks < 0) return fail(FOE_EINVAL, "max_backtracks must be >= 0");
@@ -302,8 +324,8 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
     if (!std::isfinite(filters[i])) return fail(FOE_EINVAL, "non-finite filter tap");
     if (!(std::fabs(filters[i]) < SPLIT_MAX_TAP)) split_ok = false;
   }
-  if (p->engine == FOE_ENGINE_MFMA_SPLIT && !split_ok)
-    return fail(FOE_EINVAL, "the split-FP16 engine takes taps with |k| < 16384");
+  if ((p->engine == FOE_ENGINE_MFMA_SPLIT || p->precision == FOE_PREC_BF16) && !split_ok)
+    return fail(FOE_EINVAL, "the split-FP16 engine (also the forward of BF16 precision) takes taps with |k| < 16384");
   for (int i = 0; i < p->num_filters; ++i)
     if (!(std::isfinite(weights[i]) && weights[i] >= 0.0f)) return fail(FOE_EINVAL, "weights must be finite, >= 0");
   pb->nf = p->num_filters;
@@ -358,7 +380,7 @@ void destroy_all(foe_solver* s) {
   if (s->graph_one1) (void)hipGraphExecDestroy(s->graph_one1);
   for (float* p : s->xr) if (p) (void)hipFree(p);
   for (float* p : s->gr) if (p) (void)hipFree(p);
-  void* bufs[] = {s->fbuf, s->scratch, s->zbuf, s->kf, s->ka, s->kf16, s->theta, s->partials, s->partials2, s->stats, s->st, s->st2,
+  void* bufs[] = {s->fbuf, s->scratch, s->zbuf, s->kf, s->ka, s->kf16, s->kb16, s->theta, s->partials, s->partials2, s->stats, s->st, s->st2,
                   s->d_images, s->d_tiles};
   for (void* b : bufs) if (b) (void)hipFree(b);
   if (s->st_host) (void)hipHostFree(s->st_host);
@@ -561,6 +583,7 @@ foe_status create_common(const foe_params* p, int n_img, const int32_t* H, const
   if (p->fusion == FOE_UNFUSED) ok = ok && alloc((void**)&s->zbuf, plane * p->num_filters);
   ok = ok && alloc((void**)&s->kf, sizeof(float) * MAX_NF * KK) && alloc((void**)&s->ka, sizeof(float) * MAX_NF * KK);
   ok = ok && alloc((void**)&s->kf16, sizeof(unsigned) * (MAX_NF / V_NC) * F16_OPS);
+  ok = ok && alloc((void**)&s->kb16, sizeof(unsigned) * MAX_NF * KB16_W);
   ok = ok && alloc((void**)&s->theta, sizeof(float) * MAX_NF);
   ok = ok && alloc((void**)&s->partials, sizeof(double) * PART_COLS * (size_t)s->max_tiles);
   ok = ok && alloc((void**)&s->partials2, sizeof(double) * PART_COLS * (size_t)s->max_tiles);
@@ -582,6 +605,7 @@ foe_status create_common(const foe_params* p, int n_img, const int32_t* H, const
   hipError_t e = hipMemcpy(s->kf, tabs->kf, sizeof(tabs->kf), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->kf16, tabs->kf16, sizeof(tabs->kf16), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->ka, tabs->ka, sizeof(tabs->ka), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->kb16, tabs->kb16, sizeof(tabs->kb16), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->theta, tabs->theta, sizeof(tabs->theta), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreate(&s->ev0);
   if (e == hipSuccess) e = hipEventCreate(&s->ev1);
@@ -931,12 +955,14 @@ constexpr int NOALLOC_MAX_DEVICES = 64;
 __device__ __align__(256) unsigned char noalloc_scratch[NOALLOC_BYTES];
 void* g_noalloc_base[NOALLOC_MAX_DEVICES] = {};
 std::mutex g_noalloc_mu;
+std::mutex g_noalloc_call_mu;
+TapTables g_noalloc_tabs;   // host tap tables of the current call (static: no heap, no large stack frame)
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Byte offsets of the buffers of a one-image solve inside the workspace (32 x 32 tiles).
 struct NoallocLayout {
-  size_t xr[3], gr[2], partials, partials2, stats, st, st2, images, tiles, kf, ka, kf16, theta, total;
+  size_t xr[3], gr[2], partials, partials2, stats, st, st2, images, tiles, kf, ka, kf16, kb16, theta, total;
 };
 
 NoallocLayout noalloc_layout(size_t n, int ntiles, int stats_rows) {
@@ -955,6 +981,7 @@ NoallocLayout noalloc_layout(size_t n, int ntiles, int stats_rows) {
   l.kf = take(sizeof(float) * MAX_NF * KK);
   l.ka = take(sizeof(float) * MAX_NF * KK);
   l.kf16 = take(sizeof(unsigned) * (MAX_NF / V_NC) * F16_OPS);
+  l.kb16 = take(sizeof(unsigned) * MAX_NF * KB16_W);
   l.theta = take(sizeof(float) * MAX_NF);
   l.total = o;
   return l;
@@ -1066,9 +1093,12 @@ foe_status foe_solve_noalloc(const foe_params* p, const float* filters_host, con
   if (v != FOE_OK) return v;
   unsigned char* b = static_cast<unsigned char*>(base);
 
+  // one call at a time per process: the host tap tables are static, and calls that overlap on a GPU race
+  // on its workspace anyway
+  std::lock_guard<std::mutex> lock(g_noalloc_call_mu);
   foe_solver s;   // its containers stay empty: nothing here allocates
   DevState st_host{};
-  TapTables tabs;
+  TapTables& tabs = g_noalloc_tabs;
   s.p = *p;
   s.pb = pb;
   s.stream = (hipStream_t)hip_stream;
@@ -1092,12 +1122,14 @@ foe_status foe_solve_noalloc(const foe_params* p, const float* filters_host, con
   s.kf = reinterpret_cast<float*>(b + l.kf);
   s.ka = reinterpret_cast<float*>(b + l.ka);
   s.kf16 = reinterpret_cast<unsigned*>(b + l.kf16);
+  s.kb16 = reinterpret_cast<unsigned*>(b + l.kb16);
   s.theta = reinterpret_cast<float*>(b + l.theta);
 
   build_tap_tables(p->num_filters, filters_host, weights_host, &tabs);
   HIP_OR(hipMemcpyAsync(s.kf, tabs.kf, sizeof(tabs.kf), hipMemcpyHostToDevice, s.stream));
   HIP_OR(hipMemcpyAsync(s.ka, tabs.ka, sizeof(tabs.ka), hipMemcpyHostToDevice, s.stream));
   HIP_OR(hipMemcpyAsync(s.kf16, tabs.kf16, sizeof(tabs.kf16), hipMemcpyHostToDevice, s.stream));
+  HIP_OR(hipMemcpyAsync(s.kb16, tabs.kb16, sizeof(tabs.kb16), hipMemcpyHostToDevice, s.stream));
   HIP_OR(hipMemcpyAsync(s.theta, tabs.theta, sizeof(tabs.theta), hipMemcpyHostToDevice, s.stream));
   HIP_OR(hipMemcpyAsync(s.d_images, &im, sizeof(ImageDesc), hipMemcpyHostToDevice, s.stream));
   tile_list_kernel<<<(ntiles + 255) / 256, 256, 0, s.stream>>>(s.d_tiles, ntx, ntiles, tc.tw, tc.th);

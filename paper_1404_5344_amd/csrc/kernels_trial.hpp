@@ -1,6 +1,8 @@
-// Fused FoE trial kernel.  The forward bank runs on one of four engines: the split-FP16 matrix-core
-// engine (FP32 operands as FP16 heads and scaled tails), the FP32 matrix-core engine, the BF16
-// matrix-core engine, or the VALU direct convolution; the rest of the trial is the same code.
+// Fused FoE trial kernel.  The filter bank runs on one of four engines: the split-FP16 matrix-core
+// engine (forward bank with FP32 operands as FP16 heads and scaled tails, adjoint on the VALU), the FP32
+// matrix-core engine (forward), the BF16 engine (the split-FP16 forward, so that the energies of the line
+// search keep FP32 accuracy, and the adjoint bank as a BF16 matrix-core GEMM), or the VALU direct
+// convolution; the rest of the trial is the same code.
 //
 // One workgroup owns one TH x TW output tile and runs, entirely on chip:
 //   1. the inertial step and the pointwise prox on the tile + 6-pixel halo
@@ -23,6 +25,7 @@
 namespace foe {
 
 enum FusedMode { MODE_TRIAL = 0, MODE_EVAL = 1 };
+// Engines: FWD_MFMA_BF16 takes the forward of FWD_MFMA_F16X and the BF16 matrix-core adjoint (ZStrips).
 enum ForwardEngine { FWD_VALU = 0, FWD_MFMA_F32 = 1, FWD_MFMA_BF16 = 2, FWD_MFMA_F16X = 3 };
 // Fusion of the gradient: the whole trial in one kernel (FUSED), or split in two launches that
 // exchange the 48 z planes through HBM: FWD_HALF runs stages 1-2 (step, prox, forward bank,
@@ -58,6 +61,8 @@ struct FusedArgs {
   const float* ka;                      // adjoint taps: ka[i][a][b] = 2 theta_i k_i[a][b]
   const unsigned* kf16;                 // split-FP16 forward operands: per chunk, F16_OPS words in the
                                         //   lane order of the split engine (ForwardOps<FWD_MFMA_F16X>)
+  const unsigned* kb16;                 // BF16 adjoint operands (matrix-core adjoint): KB16_W words per
+                                        //   filter (ZStrips)
   const float* theta;
   float* zbuf;                          // unfused z planes: zbuf[i * zstride + off + y * W + x]
   long long zstride;
@@ -81,17 +86,30 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* red, dou
   }
 }
 
+// z lines of the fold: Z_r[s] = z at line r, position s along the line, from FP32 planes (B16 = false) or
+// from the BF16 engine's strips (B16 = true).
+template <int ZS, int ZL, bool B16 = false>
+struct ZLines {
+  const void* p;
+  __device__ __forceinline__ float operator()(int r, int s) const {
+    if constexpr (B16)
+      return (float)static_cast<const __bf16*>(p)[r * ZL + s * ZS];
+    else
+      return static_cast<const float*>(p)[r * ZL + s * ZS];
+  }
+};
+
 // The mirror terms of FB consecutive positions along an edge for one filter: v_i(d) = sum_{r <= 2 - d}
-// <K_{d+r}, Z_r[i .. i + 6]> with Z_r[s] = zb[r ZL + s ZS] (s = 0 .. FB + 5) and K_m[t] = kb[m KL + t KT],
+// <K_{d+r}, Z_r[i .. i + 6]> with Z_r[s] = zl(r, s) (s = 0 .. FB + 5) and K_m[t] = kb[m KL + t KT],
 // added to out[(i R + d) NC] (each partial has one writer per chunk).  The z lines slide through
 // registers, the tap lines are loaded once.
-template <int FB, int NC, int ZS, int ZL, int KT, int KL>
-__device__ __forceinline__ void fold_block(const float* zb, const float* kb, float* out) {
+template <int FB, int NC, int KT, int KL, class ZL>
+__device__ __forceinline__ void fold_block(ZL zl, const float* kb, float* out) {
   float Z[R][FB + KS - 1], K[R][KS];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
 #pragma unroll
-    for (int s = 0; s < FB + KS - 1; ++s) Z[r][s] = zb[r * ZL + s * ZS];
+    for (int s = 0; s < FB + KS - 1; ++s) Z[r][s] = zl(r, s);
 #pragma unroll
     for (int t = 0; t < KS; ++t) K[r][t] = kb[r * KL + t * KT];
   }
@@ -135,15 +153,17 @@ template <> struct ForwardOps<FWD_MFMA_F16X> {
   half8 hi[2], lo[2];   // A operands of the two steps (FP16 heads, 4096-scaled tails)
   float sc, sclo;       // 2^E and 2^(E - 12)
 };
+template <> struct ForwardOps<FWD_MFMA_BF16> : ForwardOps<FWD_MFMA_F16X> {};
 
 // Row stride of the z planes (the tile + 3 halo, TW + 6 wide): the split engine pads it to a multiple of 8
 // floats, so that the adjoint's 10-wide window rows load as two 16-byte reads and a pair, and the
 // 2 x 8 position patches of its forward store z into distinct LDS banks.
-constexpr int z_row_stride(int tw, int fwd) { return fwd == FWD_MFMA_F16X ? (tw + 2 * R + 7) / 8 * 8 : tw + 2 * R; }
+constexpr bool split_forward(int fwd) { return fwd == FWD_MFMA_F16X || fwd == FWD_MFMA_BF16; }
+constexpr int z_row_stride(int tw, int fwd) { return split_forward(fwd) ? (tw + 2 * R + 7) / 8 * 8 : tw + 2 * R; }
 // Stride of the z planes: with padded rows the plane is padded too, to 4 (mod 64) floats, so that lanes
 // that read the same position of 16 different planes (the fold) fall in 16 different banks.
 constexpr int z_plane_stride(int tw, int th, int fwd) {
-  return fwd == FWD_MFMA_F16X ? (th + 2 * R) * z_row_stride(tw, fwd) + ((4 - (th + 2 * R) * z_row_stride(tw, fwd) % 64) % 64 + 64) % 64
+  return split_forward(fwd) ? (th + 2 * R) * z_row_stride(tw, fwd) + ((4 - (th + 2 * R) * z_row_stride(tw, fwd) % 64) % 64 + 64) % 64
                               : (th + 2 * R) * (tw + 2 * R);
 }
 
@@ -179,6 +199,36 @@ __device__ __forceinline__ void split_store(unsigned* u16w, int r, int c, float 
     q[2 * SP::COPY1 - 1 + SP::COLS] = lo;
   }
 }
+
+// z planes of the BF16 engine's matrix-core adjoint.  The adjoint of one filter on a 16 x 16 output block
+// (rows r0 .. r0 + 15, columns 16 s .. 16 s + 15 of the tile) is a Toeplitz GEMM on
+// v_mfma_f32_16x16x32_bf16:
+//   g(r0 + m, 16 s + n) = sum_{a, b} ka[a][b] z3(r0 + m + a, 16 s + n + b) = sum_k A[m][k] B[k][n],
+// with the z window of the block kept as a strip of W = 22 columns (16 + 6) per row, flattened row-major:
+// A[m][k] = strip(r0 + m)[k] for k = 22 a + c (k < 160: the flattening runs on into the next rows, which meet
+// zero taps), and B[k][n] = T[k - n], T[22 a + b] = ka[a][b] for b < 7, zero for b in [7, 22) and outside
+// [0, 154).  A tile of TW = 32 columns takes two strips (z3 columns 0 .. 21 and 16 .. 37).  Operands are
+// BF16 (z in [-1/2, 1/2] and the taps each rounded once), products and sums FP32.  Layout per filter j:
+// strips 0, 1 of STRIP_H halves each; a padding of 8 halves after the last filter holds zeros (the last rows'
+// k >= 154 reads).
+template <int TW, int TH>
+struct ZStrips {
+  static constexpr int H3 = TH + 2 * R, W3 = TW + 2 * R;
+  static constexpr int W = 22;                       // strip columns: 16 outputs + 6
+  static constexpr int NS = TW / 16;                 // strips per tile row
+  static constexpr int STRIP_H = H3 * W;             // halves per strip
+  static constexpr int FILTER_H = NS * STRIP_H;      // halves per filter
+  static constexpr int KSTEPS = (KS * W + 31) / 32;  // 32-wide K steps: 5
+  static constexpr int NB = (TH / 16) * NS;          // 16 x 16 output blocks per tile
+  static_assert(TW == 32 && TH % 16 == 0 && W3 == 16 * (NS - 1) + W, "two strips cover the tile + 3 halo");
+  static_assert(KSTEPS * 32 - KS * W <= W, "the flattened K range ends inside the next row");
+};
+// BF16 adjoint tap operands in global memory, per filter: T padded by 16 zeros in front and zeros behind, in
+// two copies (copy 1 shifted by one half), so that the 8 consecutive values T[32 s + 8 kb - n .. + 7] of lane
+// (n, kb) start on a 4-byte boundary in copy n & 1.  Word w of copy c of filter i: kb16[i * KB16_W + c *
+// KB16_COPY + w].
+constexpr int KB16_COPY = 88;               // 176 halves: T[-16 .. 159]
+constexpr int KB16_W = 2 * KB16_COPY;
 
 // The live and own bits (bits 2i and 2i + 1) of the passes i of lane m of wave g0 in the split engine's
 // 2 x 8 patch groups: the same in every chunk, so they are formed once per launch.
@@ -236,10 +286,14 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
   constexpr int W6 = TW + 4 * R, W3 = TW + 2 * R, H3 = TH + 2 * R;
   constexpr int ZW = z_row_stride(TW, FWD), PLANE = z_plane_stride(TW, TH, FWD), PLANE3 = H3 * W3;
   constexpr int TLAST = (KS - 1) * W6 + (KS - 1);
+  // the fused BF16 engine keeps z as BF16 strips for its matrix-core adjoint (ZStrips)
+  constexpr bool ZSPLIT = FWD == FWD_MFMA_BF16 && FUSION == FUSED;
   float ef = 0.0f;
   // one group: this lane's position (rr, cc) of the R3 region; live: z is kept (in the image, or periodic);
-  // own: a tile position in the image, whose energy counts
-  auto group = [&](int rr, int cc, const unsigned* b, float* zq, bool live, bool own) {
+  // own: a tile position in the image, whose energy counts.  zq: the position in plane 0 (FP32 planes);
+  // zh0 / zh1: the position in strip 0 / 1 of filter 0, stored when s0 / s1 (ZSPLIT)
+  auto group = [&](int rr, int cc, const unsigned* b, float* zq, __bf16* zh0, __bf16* zh1, bool s0, bool s1,
+                   bool live, bool own) {
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (FWD == FWD_MFMA_F32) {
       const int pbase = rr * W6 + cc;
@@ -269,15 +323,42 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       for (int j = 0; j < 4; ++j) acc[j] = UNIT ? fmaf(cr[j], 1.0f / 4096.0f, hh[j]) : fmaf(cr[j], ops.sclo, hh[j] * ops.sc);
     }
     const int gy = y0 - R + rr, gx = x0 - R + cc;
-    float e = 0.0f;
+    float e = 0.0f, zv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float yv = acc[j];
       const float den = fmaf(yv, yv, 1.0f);
       const float z = yv * fast_rcp(den);
-      zq[(4 * lk + j) * PLANE] = live ? z : 0.0f;   // zq: this position in plane 0
+      zv[j] = live ? z : 0.0f;
+      if constexpr (!ZSPLIT) zq[(4 * lk + j) * PLANE] = zv[j];   // zq: this position in plane 0
       if (FUSION == FWD_HALF && own && 4 * lk + j < nlive) zb[(4 * lk + j) * zstride + (long long)gy * W + gx] = z;
       e = fmaf(thl[j], __builtin_amdgcn_logf(den), e);   // theta ln 2 * log2(1 + y^2)
+    }
+    if constexpr (ZSPLIT) {
+      // BF16 pairs of two neighbouring columns: lanes 2i and 2i + 1 of a row hold columns cc and cc + 1 of the
+      // same four filters; they swap two values (DPP quad_perm 1, 0, 3, 2), then the even lane stores filters
+      // 4k, 4k + 1 and the odd lane filters 4k + 2, 4k + 3 as one word each (low half = the even column)
+      const bool odd = lm & 1;   // the lane's column parity (cc = 8 cb + (lm & 7))
+      const float ra = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(odd ? zv[0] : zv[2]), 0xb1, 0xf, 0xf, false));
+      const float rb = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(odd ? zv[1] : zv[3]), 0xb1, 0xf, 0xf, false));
+      auto pack = [](float lo, float hi) {
+        return (unsigned)__builtin_bit_cast(unsigned short, (__bf16)lo) |
+               ((unsigned)__builtin_bit_cast(unsigned short, (__bf16)hi) << 16);
+      };
+      const unsigned wa = odd ? pack(ra, zv[2]) : pack(zv[0], ra);
+      const unsigned wb = odd ? pack(rb, zv[3]) : pack(zv[1], rb);
+      const int fo = (4 * lk + (odd ? 2 : 0)) * ZStrips<TW, TH>::FILTER_H - (odd ? 1 : 0);
+      constexpr int FW = ZStrips<TW, TH>::FILTER_H / 2;
+      if (s0) {
+        unsigned* w = reinterpret_cast<unsigned*>(zh0 + fo);
+        w[0] = wa;
+        w[FW] = wb;
+      }
+      if (s1) {
+        unsigned* w = reinterpret_cast<unsigned*>(zh1 + fo);
+        w[0] = wa;
+        w[FW] = wb;
+      }
     }
     ef += own ? e : 0.0f;
   };
@@ -297,7 +378,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
     for (; g < NFULL; g += GS) {
       bool live, own;
       masks(r, c, live, own);
-      group(r, c, u16, zp + r * ZW + c, live, own);
+      group(r, c, u16, zp + r * ZW + c, nullptr, nullptr, false, false, live, own);
       p += STEP;
       c += DC;
       r += DR;
@@ -310,7 +391,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       const int rr = p < PLANE3 ? r : 0, cc = p < PLANE3 ? c : 0;
       bool live, own;
       masks(rr, cc, live, own);
-      group(rr, cc, u16, zp + rr * ZW + cc, live, own);
+      group(rr, cc, u16, zp + rr * ZW + cc, nullptr, nullptr, false, false, live, own);
     }
   } else {
     // groups of 2 x 8 positions (lane m: row m / 8, column m % 8 of the patch), patch rows of NCB
@@ -330,10 +411,15 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
     int rr = 2 * rp + dy, cc = cb * 8 + dx;
     const unsigned* b = u16 + (cc & 1) * SP::COPY1 + (rr + lk) * SP::ROW_W + (cc >> 1);
     float* zq = zp + rr * ZW + cc;
+    // ZSPLIT: strip 0 takes the columns < 22, strip 1 the columns 16 .. W3 - 1 (never the padding columns)
+    constexpr int SW = 22, SH = ZSPLIT ? ZStrips<TW, TH>::STRIP_H : 0;
+    constexpr int DZH = DR * SW + DC, DZH_WRAP = (DR + 2) * SW + DC - 8 * NCB;
+    __bf16* zh0 = reinterpret_cast<__bf16*>(zp) + rr * SW + cc;
+    __bf16* zh1 = zh0 + SH - 16;
     unsigned m = pmask;
 #pragma unroll 1
     for (int g = g0; g < NG; g += GS) {
-      group(rr, cc, b, zq, ALL_IN || (m & 1u), (m & 2u) != 0u);
+      group(rr, cc, b, zq, zh0, zh1, cc < SW, cc >= 16 && cc < W3, ALL_IN || (m & 1u), (m & 2u) != 0u);
       m >>= 2;
       cb += GS % NCB;
       const bool wrap = cb >= NCB;
@@ -341,7 +427,12 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
       rr += wrap ? DR + 2 : DR;
       cc += wrap ? DC - 8 * NCB : DC;
       b += wrap ? DBW_WRAP : DBW;
-      zq += wrap ? DZO_WRAP : DZO;
+      if constexpr (ZSPLIT) {
+        zh0 += wrap ? DZH_WRAP : DZH;
+        zh1 += wrap ? DZH_WRAP : DZH;
+      } else {
+        zq += wrap ? DZO_WRAP : DZO;
+      }
     }
   }
   return ef;
@@ -389,26 +480,35 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   static_assert(BC % 2 == 0 && ZW % 2 == 0 && PLANE % 2 == 0, "adjoint reads float2 pairs");
   constexpr bool WIN4 = ZW % 4 == 0 && BC % 4 == 0 && PLANE % 4 == 0;   // window rows start on 16 bytes
   static_assert(NC % 8 == 0, "forward passes take 8 filters");
-  static_assert(NG * TH * TW <= NC * PLANE, "epilogue does not fit in the z buffer");
+
   static_assert((NC & (NC - 1)) == 0 && TH >= R && TW >= R, "fold items: NC a power of two, tiles >= 3");
   static_assert(FWD == FWD_VALU || NC == 16, "the MFMA forwards take one 16-filter block per chunk");
   static_assert(KK % 4 == 1, "the FP32 matrix-core forward takes taps 0 .. KK - 2 in steps of 4");
   constexpr int NGROUP = (PLANE3 + 15) / 16;      // MFMA forward: groups of 16 consecutive positions
 
+  constexpr bool SPLIT = split_forward(FWD);   // the split-FP16 forward
+  // the BF16 engine's fused kernel and adjoint half: z as BF16 strips, the adjoint bank on the matrix cores
+  // (ZStrips)
+  constexpr bool ZSPLIT = FWD == FWD_MFMA_BF16 && (UNF == FUSED || UNF == ADJ_HALF);
+  using ZS = ZStrips<TW, TH>;
+  constexpr int ZS_WORDS = (NC * ZS::FILTER_H + 8) / 2;   // strips of the chunk + the zero padding
+  constexpr int ZP_FLOATS = ZSPLIT ? (ZS_WORDS > NG * TH * TW ? ZS_WORDS : NG * TH * TW) : NC * PLANE;
+  static_assert(NG * TH * TW <= ZP_FLOATS, "epilogue does not fit in the z buffer");
+  static_assert(!ZSPLIT || NT / 64 == NC, "the matrix-core adjoint takes one filter of the chunk per wave");
   __shared__ float u6[H6 * W6];
-  __shared__ __attribute__((aligned(16))) float zp[NC * PLANE];
+  __shared__ __attribute__((aligned(16))) float zp[ZP_FLOATS];
   __shared__ float fpart[NSLOT * R * NC];  // fold partials [slot][d][filter of the chunk], over chunks
   __shared__ double red[(NT / 64) * 5];
   // taps of the current chunk, read by broadcast LDS loads so that the FMAs take them from VGPRs
   // (a VALU FMA with an SGPR operand issues at half rate on gfx950)
   constexpr int KAP = 52;                                   // padded adjoint tap stride (16 B rows)
-  constexpr bool SPLIT = FWD == FWD_MFMA_F16X;
   constexpr int KF_N = SPLIT ? F16_OPS : KK * NC;           // forward tap words per chunk
   __shared__ __attribute__((aligned(16))) float kf_s[KF_N];      // [t][j], or the split operands by lane
   __shared__ __attribute__((aligned(16))) float ka_s[NC * KAP];  // [j][t]
   using SP = SplitPlanes<TW, TH>;
   __shared__ __attribute__((aligned(16))) unsigned u16w[SPLIT ? SP::WORDS : 1];
   __shared__ float wmax[SPLIT ? NT / 64 : 1];
+
 
   const int tid = threadIdx.x;
   const Problem pb = a.pb;
@@ -420,8 +520,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   const int x0 = td.x0, y0 = td.y0;
 
   // taps of the next chunk, fetched one chunk ahead (chunk 0: before stage 1) so that their HBM latency
-  // is hidden behind the work in between (the BF16 engine, short of registers, fetches at chunk start)
-  constexpr bool PREFETCH = FWD != FWD_MFMA_BF16;
+  // is hidden behind the work in between
+  constexpr bool PREFETCH = true;
   constexpr int KF_PT = (KF_N + NT - 1) / NT, KA_PT = (NC * KAP + NT - 1) / NT;
   float kfr[KF_PT], kar[KA_PT];
   auto fetch_taps = [&](int cn) {
@@ -601,6 +701,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         }
         h[cp * COPY_H + row * ROW_H + part * SP::COLS + col] = (_Float16)0.0f;
       }
+      if constexpr (ZSPLIT)   // the halves after the last strip, read by the last rows' k >= 154 (zero taps)
+        if (tid < 4) reinterpret_cast<unsigned*>(zp)[NC * ZS::FILTER_H / 2 + tid] = 0u;
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) umx = fmaxf(umx, __shfl_xor(umx, o));
       if ((tid & 63) == 0) wmax[tid >> 6] = umx;
@@ -681,6 +783,15 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   if constexpr (SPLIT)   // the wave index is uniform: the patch counters live in scalar registers
     pmask = patch_masks<TW, TH, NT / 64>(__builtin_amdgcn_readfirstlane(tid >> 6), tid & 15, y0, x0, H, W, bc == PERIODIC);
 
+  // matrix-core adjoint (ZSPLIT): this wave's filter of each chunk on the NB output blocks of the tile, summed
+  // over the chunks in gacc
+  constexpr int NBZ = ZSPLIT ? ZS::NB : 1;
+  floatx4 gacc[NBZ];
+#pragma unroll
+  for (int q = 0; q < NBZ; ++q) gacc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index (uniform)
+  const int ln = tid & 15, lkb = (tid >> 4) & 3;            // lane (n, kb) of the 16 x 16 x 32 operands
+
   const int nf = pb.nf;
   for (int c0 = 0; c0 < nf; c0 += NC) {
     const int ncur = min(NC, nf - c0);
@@ -714,81 +825,22 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         float zv[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) zv[j] = flive[k] && j < ncur ? src[(size_t)j * a.zstride] : 0.0f;
+        if constexpr (ZSPLIT) {
+          // the strips of the fused BF16 kernel (the same rounding of the same FP32 z, so both paths give the
+          // same bits): strip 0 for the columns < 22, strip 1 for the columns >= 16
+          __bf16* zh = reinterpret_cast<__bf16*>(zp) + r * ZS::W + c;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) zp[j * PLANE + zofs[k]] = zv[j];
-      }
-    } else if constexpr (FWD == FWD_MFMA_BF16) {
-      // ---- stage 2 (matrix cores, BF16 operands, FP32 accumulation): v_mfma_f32_16x16x32_bf16 with
-      // lane (m = lane % 16, k = lane / 16) holding taps 32s + 8k .. 32s + 8k + 7 of filter m (A) and the
-      // same taps of position m (B).  The B values are differences u(p + t) - u(p) to the position's own
-      // sample, so that BF16 rounding acts on local contrast and not on the 8-bit intensity level
-      // (zero-sum filters applied to flat regions would otherwise drown in rounding noise); the exact
-      // FP32 term u(p) * sum_t k[t] is added back after the product.  Each operand is split into a BF16
-      // head and a BF16 tail (x = hi + lo), and three products hi*hi + hi*lo + lo*hi are accumulated,
-      // which keeps the energies of the line search at close to FP32 accuracy.
-      const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lm = lane & 15, lk = lane >> 4;
-      bf16x8 a16[2], a16lo[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int t = 32 * s + 8 * lk + i;
-          const float kv = t < KK ? kf_s[t * NC + lm] : 0.0f;
-          a16[s][i] = (__bf16)kv;
-          a16lo[s][i] = (__bf16)(kv - (float)a16[s][i]);
-        }
-      float thv[4], ksum[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int fj = 4 * lk + j;
-        thv[j] = fj < ncur ? a.theta[c0 + fj] : 0.0f;
-        float sum = 0.0f;
-        for (int t = 0; t < KK; ++t) sum += kf_s[t * NC + fj];
-        ksum[j] = sum;
-      }
-#pragma unroll 1
-      for (int g = wave; g < NGROUP; g += NT / 64) {
-        const int p = g * 16 + lm;
-        const bool inr = p < PLANE3;
-        const int r = inr ? p / W3 : 0, c = inr ? p - (p / W3) * W3 : 0;
-        const int pbase = r * W6 + c;
-        const float uc = u6[pbase + R * W6 + R];
-        floatx4 acc4 = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          bf16x8 b16, b16lo;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int t = 32 * s + 8 * lk + i;
-            const int toff = t < KK ? (t / KS) * W6 + (t % KS) : 0;
-            const float d = u6[pbase + toff] - uc;
-            b16[i] = (__bf16)d;
-            b16lo[i] = (__bf16)(d - (float)b16[i]);
+          for (int j = 0; j < NC; ++j) {
+            const __bf16 hv = (__bf16)zv[j];
+            if (c < ZS::W) zh[j * ZS::FILTER_H] = hv;
+            if (c >= 16) zh[j * ZS::FILTER_H + ZS::STRIP_H - 16] = hv;
           }
-          acc4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a16lo[s], b16, acc4, 0, 0, 0);
-          acc4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a16[s], b16lo, acc4, 0, 0, 0);
-          acc4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a16[s], b16, acc4, 0, 0, 0);
-        }
-        const int gy = y0 - R + r, gx = x0 - R + c;
-        const bool inimg = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-        const bool live = inr && (inimg || bc == PERIODIC);
-        const bool own = inr && inimg && r >= R && r < R + TH && c >= R && c < R + TW;
-        const int zo = r * ZW + c;
-        // the position's u(p) is the same for the 4 filters of this lane; fetch it per lane
-        float e = 0.0f;
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float yv = fmaf(uc, ksum[j], acc4[j]);
-          const float den = fmaf(yv, yv, 1.0f);
-          const float z = yv * fast_rcp(den);
-          if (inr) zp[(4 * lk + j) * PLANE + zo] = live ? z : 0.0f;
-          if (UNF == FWD_HALF && own && 4 * lk + j < ncur)
-            a.zbuf[(size_t)(c0 + 4 * lk + j) * a.zstride + im.off + (size_t)gy * W + gx] = z;
-          e = fmaf(thv[j], fast_log(den), e);
+          for (int j = 0; j < NC; ++j) zp[j * PLANE + zofs[k]] = zv[j];
         }
-        if (own) accF += (double)e;
       }
-    } else if constexpr (FWD == FWD_MFMA_F32 || FWD == FWD_MFMA_F16X) {
+    } else if constexpr (FWD == FWD_MFMA_F32 || SPLIT) {
       // ---- stage 2 (matrix cores): per group of 16 consecutive R3 positions,
       // Y^T[16 filters x 16 positions] = Kflip^T[16 x taps] . X[taps x 16 positions].  FP32 engine:
       // twelve v_mfma_f32_16x16x4f32 over taps 0..47 and the last tap (48) on the VALU; lane (m = lane % 16,
@@ -825,7 +877,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       // matrix pipe while this one waits for its predecessor
       float* zb = UNF == FWD_HALF ? a.zbuf + (size_t)c0 * a.zstride + im.off : nullptr;
       float ef;
-      if (FWD == FWD_MFMA_F16X && usc == 1.0f)
+      if (SPLIT && usc == 1.0f)
         ef = all_in ? mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, true, FWD, true>(
                           u6, u16w, zp, ops, thl, wave, lm, lk, y0, x0, H, W, bc == PERIODIC, zb, a.zstride, ncur, pmask)
                     : mfma_forward_chunk<TW, TH, NC, NT / 64, UNF, false, FWD, true>(
@@ -889,12 +941,47 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         if (fown[k]) accF += (double)e;
       }
     }
+    // matrix-core adjoint: the B operands (Toeplitz tap rows) of this wave's filter for every K step, fetched
+    // before the barrier so that their latency overlaps the wait; lane (n, kb) of step s takes
+    // T[32 s + 8 kb - n .. + 7] from copy n & 1
+    constexpr int KST = ZSPLIT ? ZS::KSTEPS : 1;
+    u32x4 bw[KST];
+    if constexpr (ZSPLIT) {
+      if (wv < ncur) {
+        const unsigned* tb = a.kb16 + (size_t)(c0 + wv) * KB16_W + (ln & 1) * KB16_COPY + ((16 - ln - (ln & 1)) >> 1) +
+                             4 * lkb;
+#pragma unroll
+        for (int st = 0; st < KST; ++st) {
+          const unsigned* th = tb + 16 * st;
+          bw[st] = u32x4{th[0], th[1], th[2], th[3]};
+        }
+      }
+    }
     __syncthreads();
 
-    // ---- stage 3: adjoint bank.  Per filter of the group: the BR x BC block of this thread from a
-    // (BR+6) x (BC+6) window in registers; then, on fold tiles, the fold items of the chunk.
+    // ---- stage 3: adjoint bank.
+    // ZSPLIT: wave wv takes filter wv of the chunk on every 16 x 16 output block (ZStrips): per K step one
+    // v_mfma_f32_16x16x32_bf16, A = the block's z strip rows, B = the Toeplitz taps; FP32 sums in gacc.
+    if constexpr (ZSPLIT) {
+      if (wv < ncur) {
+        const __bf16* zw = reinterpret_cast<const __bf16*>(zp) + wv * ZS::FILTER_H + ln * ZS::W + 8 * lkb;
+#pragma unroll
+        for (int st = 0; st < KST; ++st) {
+          const bf16x8 bb = __builtin_bit_cast(bf16x8, bw[st]);
+#pragma unroll
+          for (int q = 0; q < NBZ; ++q) {
+            const int rb = q / ZS::NS, sb = q - rb * ZS::NS;
+            const unsigned* pa = reinterpret_cast<const unsigned*>(zw + sb * ZS::STRIP_H + 16 * rb * ZS::W + 32 * st);
+            const bf16x8 ab = __builtin_bit_cast(bf16x8, u32x4{pa[0], pa[1], pa[2], pa[3]});
+            gacc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb, gacc[q], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // VALU: per filter of the group the BR x BC block of this thread from a (BR+6) x (BC+6) window in
+    // registers.  Then, on fold tiles, the fold items of the chunk.
 #pragma unroll 1
-    for (int jj = 0; jj < (UNF == FWD_HALF ? 0 : FPG); ++jj) {
+    for (int jj = 0; jj < (UNF == FWD_HALF || ZSPLIT ? 0 : FPG); ++jj) {
       const int j = grp * FPG + jj;
       if (j >= ncur) break;
       float kt[KAP];
@@ -954,22 +1041,46 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           const int loc = it - (lo ? 0 : f_y1), j = loc & (NC - 1), p0 = (loc / NC) * FB;
           if (j >= ncur) continue;
           float* out = fpart + ((lo ? 0 : TW) + p0) * R * NC + j;
-          if (lo)
-            fold_block<FB, NC, 1, ZW, 1, KS>(zp + j * PLANE + R * ZW + p0, ka_s + j * KAP + (R + 1) * KS, out);
-          else
-            fold_block<FB, NC, 1, -ZW, 1, -KS>(zp + j * PLANE + (H - 1 - y0 + R) * ZW + p0,
-                                               ka_s + j * KAP + (R - 1) * KS, out);
+          const int zrow = lo ? R : H - 1 - y0 + R;   // plane row of the edge line
+          if constexpr (ZSPLIT) {
+            // the FB + 6 columns p0 .. p0 + FB + 5 lie in strip 0 when p0 < 16, else in strip 1
+            const int sb = p0 >= 16;
+            const __bf16* zl = reinterpret_cast<const __bf16*>(zp) + j * ZS::FILTER_H + sb * ZS::STRIP_H +
+                               zrow * ZS::W + p0 - 16 * sb;
+            if (lo)
+              fold_block<FB, NC, 1, KS>(ZLines<1, ZS::W, true>{zl}, ka_s + j * KAP + (R + 1) * KS, out);
+            else
+              fold_block<FB, NC, 1, -KS>(ZLines<1, -ZS::W, true>{zl}, ka_s + j * KAP + (R - 1) * KS, out);
+          } else {
+            if (lo)
+              fold_block<FB, NC, 1, KS>(ZLines<1, ZW>{zp + j * PLANE + zrow * ZW + p0}, ka_s + j * KAP + (R + 1) * KS,
+                                        out);
+            else
+              fold_block<FB, NC, 1, -KS>(ZLines<1, -ZW>{zp + j * PLANE + zrow * ZW + p0},
+                                         ka_s + j * KAP + (R - 1) * KS, out);
+          }
         } else if (it < f_c0) {
           // x edge block, tile rows p0 .. p0 + FB - 1: z lines are plane columns, taps run down tap columns
           const bool lo = it < f_x1;
           const int loc = it - (lo ? f_x0 : f_x1), j = loc & (NC - 1), p0 = (loc / NC) * FB;
           if (j >= ncur) continue;
           float* out = fpart + (2 * TW + (lo ? 0 : NPX) + p0) * R * NC + j;
-          if (lo)
-            fold_block<FB, NC, ZW, 1, KS, 1>(zp + j * PLANE + p0 * ZW + R, ka_s + j * KAP + R + 1, out);
-          else
-            fold_block<FB, NC, ZW, -1, KS, -1>(zp + j * PLANE + p0 * ZW + W - 1 - x0 + R, ka_s + j * KAP + R - 1,
-                                               out);
+          const int zcol = lo ? R : W - 1 - x0 + R;   // plane column of the edge line
+          if constexpr (ZSPLIT) {
+            // the three lines zcol, zcol -+ 1, zcol -+ 2 lie in strip 0 when zcol <= 21, else in strip 1
+            const int sb = zcol > 21;
+            const __bf16* zl = reinterpret_cast<const __bf16*>(zp) + j * ZS::FILTER_H + sb * ZS::STRIP_H +
+                               p0 * ZS::W + zcol - 16 * sb;
+            if (lo)
+              fold_block<FB, NC, KS, 1>(ZLines<ZS::W, 1, true>{zl}, ka_s + j * KAP + R + 1, out);
+            else
+              fold_block<FB, NC, KS, -1>(ZLines<ZS::W, -1, true>{zl}, ka_s + j * KAP + R - 1, out);
+          } else {
+            if (lo)
+              fold_block<FB, NC, KS, 1>(ZLines<ZW, 1>{zp + j * PLANE + p0 * ZW + zcol}, ka_s + j * KAP + R + 1, out);
+            else
+              fold_block<FB, NC, KS, -1>(ZLines<ZW, -1>{zp + j * PLANE + p0 * ZW + zcol}, ka_s + j * KAP + R - 1, out);
+          }
         } else {
           // a corner row (-1 - i or H + i) of an x edge: window rows outside the plane are off the image
           // (rows < 0 for the low corners, >= H for the high ones); they read the plane's first / last
@@ -979,7 +1090,6 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           if (j >= ncur) continue;
           const int zc0 = e == 2 ? R : W - 1 - x0 + R;            // plane column of the edge line
           const int zls = e == 2 ? 1 : -1;
-          const float* zpl = zp + j * PLANE;
           const float* kb = ka_s + j * KAP + (e == 2 ? R + 1 : R - 1);
           const int kls = e == 2 ? 1 : -1;
           const int gy = q < c_lo ? -1 - q : H + c_h0 + q - c_lo;
@@ -988,10 +1098,16 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
           float Z[R][KS], K[R][KS];
 #pragma unroll
           for (int t = 0; t < KS; ++t) {
-            const int ro = min(max(prow + t, 0), H3 - 1) * ZW;
+            const int pr = min(max(prow + t, 0), H3 - 1);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-              Z[r][t] = zpl[zc0 + ro + r * zls];
+              if constexpr (ZSPLIT) {
+                const int sb = zc0 > 21;   // the three lines share a strip (as for the x-edge blocks)
+                Z[r][t] = (float)reinterpret_cast<const __bf16*>(zp)[j * ZS::FILTER_H + sb * ZS::STRIP_H + pr * ZS::W +
+                                                                      zc0 - 16 * sb + r * zls];
+              } else {
+                Z[r][t] = zp[j * PLANE + zc0 + pr * ZW + r * zls];
+              }
               K[r][t] = kb[r * kls + t * KS];
             }
           }
@@ -1022,10 +1138,21 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     return;
   }
   float* gsum = zp;                       // [NG][TH][TW]
+  if constexpr (ZSPLIT) {
+    // lane (n, kb) of block (rb, sb) holds rows 16 rb + 4 kb + i, column 16 sb + n
 #pragma unroll
-  for (int i = 0; i < BR; ++i)
+    for (int q = 0; q < NBZ; ++q) {
+      const int rb = q / ZS::NS, sb = q - rb * ZS::NS;
 #pragma unroll
-    for (int jx = 0; jx < BC; ++jx) gsum[grp * TH * TW + (row0 + i) * TW + col0 + jx] = acc[i][jx];
+      for (int i = 0; i < 4; ++i)
+        gsum[wv * TH * TW + (16 * rb + 4 * lkb + i) * TW + 16 * sb + ln] = gacc[q][i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int jx = 0; jx < BC; ++jx) gsum[grp * TH * TW + (row0 + i) * TW + col0 + jx] = acc[i][jx];
+  }
   __syncthreads();
   for (int idx = tid; idx < TH * TW; idx += NT) {
     int i = idx / TW, jx = idx - i * TW;
