@@ -82,6 +82,18 @@ def random_bank(seed: int, nf: int = 48, ksize: int = 7) -> np.ndarray:
     return k.reshape(nf, ksize, ksize).astype(np.float32)
 
 
+def learned_style_bank(seed: int, nf: int = 48, ksize: int = 7) -> tuple[np.ndarray, np.ndarray]:
+    """Seeded filters of the kind a learned FoE bank has (Sec. II-A, Fig. 1): not zero-sum (each filter
+    keeps a random mean), norms spread log-uniformly over [0.2, 5], and weights theta_i ~ U[0.05, 5].
+    Returns (filters float32 [nf, k, k], theta float32 [nf])."""
+    r = rng(seed, 1, PURPOSE_RANDOM_BANK)
+    k = r.standard_normal((nf, ksize * ksize)) + r.uniform(-0.5, 0.5, (nf, 1))
+    k /= np.linalg.norm(k, axis=1, keepdims=True)
+    k *= np.exp(r.uniform(np.log(0.2), np.log(5.0), (nf, 1)))
+    theta = r.uniform(0.05, 5.0, nf)
+    return k.reshape(nf, ksize, ksize).astype(np.float32), theta.astype(np.float32)
+
+
 # ---------------------------------------------------------------- clean images
 def shapes_image(config_id: int, index: int, H: int, W: int, n_shapes: int = 12,
                  lo: float = 10.0, hi: float = 255.0) -> np.ndarray:

@@ -4,10 +4,12 @@
     single-image solver on that image (same tile configuration): the per-tile work and the
     per-image reductions are identical;
   * images of a batch against the FP64 oracle (free-running backtracking: final PSNR within
-    0.05 dB, the bound of the single-image backtracking runs);
+    0.05 dB, the bound of the single-image backtracking runs), and the first four images of the
+    seeded uneven batch (sides up to 960) over 300 iterations against stored oracle runs;
   * the tile-shape autotuner picks a valid configuration, caches it, and results under the
     other tile configuration stay at the parity bar.
 """
+import json
 import os
 
 import numpy as np
@@ -97,3 +99,32 @@ def test_autotuner_and_tile_configs(tmp_path):
         b.close()
     finally:
         del os.environ["FOE_TUNE_CACHE"]
+
+
+def test_uneven_batch_against_stored_oracle_runs():
+    """The first four images of the seeded uneven batch, 300 iterations each, in one batch against the stored
+    FP64 oracle runs (tests/golden/config3_oracle.json): final PSNR within 0.05 dB, the largest absolute error
+    on the stored output sample stated."""
+    import paper_1404_5344_amd as foe
+    torch, dev = torch_dev()
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config3_oracle.json")))
+    imgs = ref["images"]
+    sizes = [(im["H"], im["W"]) for im in imgs]
+    looks = [im["looks"] for im in imgs]
+    probs = [synth.config3_image(im["index"], im["H"], im["W"], im["looks"]) for im in imgs]
+    bank, theta = synth.dct_bank(), synth.theta_weights(3)
+    b = foe.BatchSolver(foe.default_params(0, 0, max_iters=300), sizes, looks, bank, theta)
+    out, sums, stats, st = b.solve(b.pack([torch.from_numpy(pr.f) for pr in probs]).to(dev))
+    outs = b.unpack(out)
+    for i, (pr, im) in enumerate(zip(probs, imgs)):
+        u = outs[i].cpu().numpy()
+        d = abs(synth.psnr(u, pr.clean) - im["psnr_final"])
+        err = np.abs(u.ravel()[im["u_sample_idx"]].astype(np.float64) - np.array(im["u_sample"]))
+        H = stats[i][-1, 0] + stats[i][-1, 1]
+        H_ora = im["F"][-1] + im["G"][-1]
+        print(f"batch image {i} {im['H']}x{im['W']} L={im['looks']}: PSNR {synth.psnr(u, pr.clean):.4f} vs oracle "
+              f"{im['psnr_final']:.4f} (diff {d:.4f} dB), energy rel diff {abs(H - H_ora) / abs(H_ora):.2e}, "
+              f"max abs err on {err.size} sampled pixels {err.max():.3e}")
+        assert sums[i]["iters_done"] == 300
+        assert d <= 0.05, (i, d)
+    b.close()
