@@ -75,6 +75,29 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
   return x;
 }
 
+// Fixed-order FP64 totals of the five partial columns {F, G, s1, s2, m} of one image's tiles, shared by every
+// kernel that decides on a trial (so that all of them round the same way): threads 0..255 of the block take
+// tiles tile0 + t, t + 256, ... in that order, the four wave sums go through red (4 x 5 doubles, shared), and
+// thread 0 receives tot[k] = ((w0 + w1) + w2) + w3.  Every thread of the block calls it (it holds a barrier).
+__device__ __forceinline__ void image_totals(const double* __restrict__ part, int tile0, int ntiles, double* red,
+                                             double (&tot)[5]) {
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (threadIdx.x < 256)
+    for (int b = tile0 + (int)threadIdx.x; b < tile0 + ntiles; b += 256)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) v[k] += part[(size_t)b * PART_COLS + k];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double x = wave_sum_f64(v[k]);
+    if (lane == 63 && wave < 4) red[wave * 5 + k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) tot[k] = red[k] + red[5 + k] + red[10 + k] + red[15 + k];
+}
+
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // e^x through the hardware 2^x
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }

@@ -40,28 +40,15 @@ __global__ void check_input_kernel(const float* __restrict__ f, const ImageDesc*
 
 enum DecideMode { DECIDE_STEP = 0, DECIDE_INIT = 1, DECIDE_REPORT = 2 };
 
-// Single-block reduction of the per-block partials in a fixed order, then by mode: REPORT stores the totals;
-// INIT also takes F(x^0) and checks the inputs; STEP settles a trial that has run and awaits its decision
-// (decide_step).  One block per image reduces the partials of that image's tiles; the first 256 threads take
-// part (every thread of the block calls it: it contains a barrier).
+// Single-block reduction of the per-block partials in the fixed order of image_totals, then by mode: REPORT
+// stores the totals; INIT also takes F(x^0) and checks the inputs; STEP settles a trial that has run and awaits
+// its decision (decide_step).  One block per image (every thread of the block calls it: it contains a barrier).
 __device__ __forceinline__ void decide_block(DevState* st, const double* __restrict__ partials, const ImageDesc& im,
                                              const Problem& pb, double* stats, int mode) {
-  __shared__ double red[256 / 64][5];
-  double v[5] = {0, 0, 0, 0, 0};
-  if (threadIdx.x < 256)
-    for (int b = im.tile0 + threadIdx.x; b < im.tile0 + im.ntiles; b += 256)
-#pragma unroll
-      for (int k = 0; k < 5; ++k) v[k] += partials[(size_t)b * PART_COLS + k];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const double x = wave_sum_f64(v[k]);
-    if (lane == 63 && wave < 4) red[wave][k] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
+  __shared__ double red[4 * 5];
   double tot[5];
-  for (int k = 0; k < 5; ++k) tot[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+  image_totals(partials, im.tile0, im.ntiles, red, tot);
+  if (threadIdx.x != 0) return;
   DevState s = *st;
   if (mode == DECIDE_STEP) {
     if (!s.pending) return;   // nothing ran since the last decision

@@ -504,7 +504,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   constexpr int KAP = 52;                                   // padded adjoint tap stride (16 B rows)
   constexpr int KF_N = SPLIT ? F16_OPS : KK * NC;           // forward tap words per chunk
   __shared__ __attribute__((aligned(16))) float kf_s[KF_N];      // [t][j], or the split operands by lane
-  __shared__ __attribute__((aligned(16))) float ka_s[NC * KAP];  // [j][t]
+  __shared__ __attribute__((aligned(16))) float ka_s[NC * KAP];  // [j][t], theta_j at t = KK
   using SP = SplitPlanes<TW, TH>;
   __shared__ __attribute__((aligned(16))) unsigned u16w[SPLIT ? SP::WORDS : 1];
   __shared__ float wmax[SPLIT ? NT / 64 : 1];
@@ -536,7 +536,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
 #pragma unroll
     for (int q = 0; q < KA_PT; ++q) {
       const int t = tid + q * NT, j = t / KAP, tt = t - j * KAP;
-      kar[q] = t < NC * KAP && tt < KK ? a.ka[(size_t)(cn + j) * KK + tt] : 0.0f;
+      kar[q] = t < NC * KAP && tt < KK ? a.ka[(size_t)(cn + j) * KK + tt]
+                                       : (t < NC * KAP && tt == KK ? a.theta[cn + j] : 0.0f);
     }
   };
   if constexpr (PREFETCH) fetch_taps(0);
@@ -554,26 +555,11 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       // the decision on the previous trial of this image: every workgroup of the image reduces the same
       // partials in the same fixed order and so takes the same decision (no inter-workgroup sync).  The
       // state is fetched together with the partials.
+      // the reduction is image_totals, the one of decide_kernel: the same totals, hence the same decision
       if (tid == 0) s_dec = *st;
-      double v[5] = {0, 0, 0, 0, 0};
-      for (int b = im.tile0 + tid; b < im.tile0 + im.ntiles; b += NT)
-#pragma unroll
-        for (int k = 0; k < 5; ++k) v[k] += a.part_in[(size_t)b * PART_COLS + k];
-      const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) v[k] = wave_sum_f64(v[k]);
-      if (lane == 63)
-#pragma unroll
-        for (int k = 0; k < 5; ++k) red[wave * 5 + k] = v[k];
-      __syncthreads();
+      double tot[5];
+      image_totals(a.part_in, im.tile0, im.ntiles, red, tot);
       if (tid == 0) {
-        double tot[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          double t = 0.0;
-          for (int w = 0; w < NT / 64; ++w) t += red[w * 5 + k];
-          tot[k] = t;
-        }
         const bool writer = (int)blockIdx.x == im.tile0;
         if (s_dec.pending && !s_dec.done) {
 #pragma unroll
@@ -596,6 +582,21 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   } else {
     xc = a.x_in + im.off;
     go = a.g_out + im.off;
+  }
+  // chunk 0's taps go to LDS now (stage 1 does not read them): their loads, issued at the start, have landed
+  // with the prologue's, and a store at the first chunk would also wait for stage 1's global stores.  Chunk 1's
+  // taps are fetched next, into the same registers.
+  auto stage_taps = [&]() {
+#pragma unroll
+    for (int q = 0; q < KF_PT; ++q)
+      if (tid + q * NT < KF_N) kf_s[tid + q * NT] = kfr[q];
+#pragma unroll
+    for (int q = 0; q < KA_PT; ++q)
+      if (tid + q * NT < NC * KAP) ka_s[tid + q * NT] = kar[q];
+  };
+  if constexpr (PREFETCH) {
+    stage_taps();
+    if (NC < pb.nf) fetch_taps(NC);
   }
   const float* __restrict__ f = a.f + im.off;
   const bool fold = UNF != FWD_HALF && bc == SYMMETRIC && (y0 < R || y0 + TH > H - R || x0 < R || x0 + TW > W - R);
@@ -796,18 +797,15 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   for (int c0 = 0; c0 < nf; c0 += NC) {
     const int ncur = min(NC, nf - c0);
     if constexpr (PREFETCH) {
-#pragma unroll
-      for (int q = 0; q < KF_PT; ++q)
-        if (tid + q * NT < KF_N) kf_s[tid + q * NT] = kfr[q];
-#pragma unroll
-      for (int q = 0; q < KA_PT; ++q)
-        if (tid + q * NT < NC * KAP) ka_s[tid + q * NT] = kar[q];
-      if (c0 + NC < nf) fetch_taps(c0 + NC);
+      if (c0 > 0) {   // chunk 0 was staged before stage 1
+        stage_taps();
+        if (c0 + NC < nf) fetch_taps(c0 + NC);
+      }
     } else {
       for (int t = tid; t < KK * NC; t += NT) kf_s[t] = a.kf[(size_t)c0 * KK + t];
       for (int t = tid; t < NC * KAP; t += NT) {
         const int j = t / KAP, tt = t - j * KAP;
-        ka_s[t] = tt < KK ? a.ka[(size_t)(c0 + j) * KK + tt] : 0.0f;
+        ka_s[t] = tt < KK ? a.ka[(size_t)(c0 + j) * KK + tt] : (tt == KK ? a.theta[c0 + j] : 0.0f);
       }
     }
     __syncthreads();
@@ -872,7 +870,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       }
       float thl[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) thl[j] = (4 * lk + j < ncur ? a.theta[c0 + 4 * lk + j] : 0.0f) * 0.6931471805599453f;
+      for (int j = 0; j < 4; ++j) thl[j] = ka_s[(4 * lk + j) * KAP + KK] * 0.6931471805599453f;   // theta ln 2
       // one position group per pass: with four waves per SIMD the other waves' chains fill the
       // matrix pipe while this one waits for its predecessor
       float* zb = UNF == FWD_HALF ? a.zbuf + (size_t)c0 * a.zstride + im.off : nullptr;
@@ -928,7 +926,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         float e = 0.0f;
   #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          float th = j < ncur ? a.theta[c0 + j] : 0.0f;
+          const float th = ka_s[j * KAP + KK];   // theta_j (zero past the bank)
           float den = fmaf(y[k][j], y[k][j], 1.0f);
           float z = y[k][j] * fast_rcp(den);
           zp[j * PLANE + zofs[k]] = flive[k] ? z : 0.0f;
