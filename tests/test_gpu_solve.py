@@ -167,6 +167,29 @@ def test_determinism_and_resume():
     s.close()
 
 
+@pytest.mark.parametrize("shape,cfg", [((1024, 1056), 0), ((640, 600), 1)])
+def test_resume_bitwise_on_images_of_many_tiles(shape, cfg):
+    """Images of more than 256 tiles (1024 x 1056: 1056 tiles of 32 x 32; 640 x 600: 760 tiles of 32 x 16): the
+    in-kernel decision and the decide kernel reduce the partials in the same order, so 2 x 30 iterations from
+    the same state give the same bits as 60."""
+    torch, dev = torch_dev()
+    H, W = shape
+    pr = synth.config2(index=4, H=H, W=W, looks=2)
+    bank, theta = synth.dct_bank(), synth.theta_weights(2)
+    s = make_solver(H, W, bank, theta, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=60, looks=2)
+    s.set_tile_config(cfg)
+    f = _gpu(pr.f, dev)
+    x0 = torch.log(f).contiguous()
+    xa, xpa = x0.clone(), x0.clone()
+    La, _, sta = s.solve_from(f, xa, xpa, 1.0, 60)
+    xb, xpb = x0.clone(), x0.clone()
+    L1, _, st1 = s.solve_from(f, xb, xpb, 1.0, 30)
+    L2, _, st2 = s.solve_from(f, xb, xpb, L1, 30)
+    assert torch.equal(xa, xb) and torch.equal(xpa, xpb) and La == L2
+    assert np.array_equal(np.concatenate([st1, st2]), sta)
+    s.close()
+
+
 def test_failure_statuses():
     import paper_1404_5344_amd as foe
     torch, dev = torch_dev()
@@ -191,3 +214,22 @@ def test_failure_statuses():
         err.max(), np.unravel_index(err.argmax(), f.shape), u.ravel()[err.argmax()], f.ravel()[err.argmax()]))
     assert err.max() <= 4e-6   # left at x^0 = log f (expf(logf(f)) round trip)
     s.close()
+
+
+def test_nonfinite_status():
+    """FOE_ENONFINITE, forced from the host through the parameters: weights theta_i = 1e38 make every term
+    theta_i log(1 + y_i^2) of F overflow the FP32 range, so F(x^0) is not finite; the solve stops at the
+    initial iterate with ENONFINITE (in either step mode) and returns u = f."""
+    import paper_1404_5344_amd as foe
+    torch, dev = torch_dev()
+    bank = synth.dct_bank()
+    theta = np.full(48, 1e38, np.float32)
+    pr = synth.config1()
+    f = _gpu(pr.f, dev)
+    for kw in (dict(step_mode=1, alpha_fixed=1e-6), {}):
+        s = make_solver(64, 64, bank, theta, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=5, **kw)
+        r = s.solve(f, allow_failure=True)
+        assert r.status == foe.ENONFINITE and r.summary["iters_done"] == 0, (kw, r.status)
+        u = r.u.cpu().numpy()
+        assert np.all(np.isfinite(u)) and np.max(np.abs(u - pr.f) / pr.f) <= 4e-6   # left at x^0 = log f
+        s.close()
