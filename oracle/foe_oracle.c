@@ -71,7 +71,11 @@ int ora_get_threads(void) {
  * pixel, or -1 where the extension is zero. */
 static int src_index(int q, int n, int bc) {
   if (q >= 0 && q < n) return q;
-  if (bc == ORA_SYMMETRIC) return q < 0 ? -1 - q : 2 * n - 1 - q;
+  if (bc == ORA_SYMMETRIC) {
+    /* half-sample mirror, repeated for sides below the filter radius: period 2n */
+    int m = ((q % (2 * n)) + 2 * n) % (2 * n);
+    return m < n ? m : 2 * n - 1 - m;
+  }
   if (bc == ORA_PERIODIC) return ((q % n) + n) % n;
   return -1;
 }
