@@ -3,8 +3,9 @@
 One step = one full solve of the 512x512 single-look workload (init, 300 iPiano iterations with
 backtracking, output) on synthetic input resident in HBM.  Prints one JSON line:
   value         Mpixel-iterations/s = H * W * accepted iterations / wall time per step
-  roofline      the fused trial kernel: algorithmic flops per launch / its mean launch duration
-                (per-launch HIP event pairs on the solver stream), against the FP32 peak; traffic =
+  roofline      the fused trial kernel: algorithmic flops per launch (9,408 per pixel: forward and adjoint
+                bank) / its mean in-solve launch duration (the solver's HIP event pair on its stream
+                around the iteration loop, over the trial launches), against the FP32 vector peak; traffic =
                 HBM bytes per launch from the committed hardware-counter summary when it was taken
                 on the current kernel sources, else null
   engines       the solver's default forward bank is the split-FP16 matrix-core engine (each FP32
@@ -71,23 +72,48 @@ def measured_traffic():
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(pr, bank, theta, seconds_target=15.0):
+def _oracle_rate(pr, bank, theta, seconds_target):
+    """The FP64 oracle on a bounded sample of the workload: Mpixel-it/s, accepted iterations, trials, seconds."""
     import oracle
     p = oracle.Params(lam1=pr.lam1, lam2=pr.lam2)
     H, W = pr.f.shape
     # calibrate on 2 iterations, then run a bounded sample
     t = time.perf_counter()
-    r = oracle.ipiano(p, pr.f, bank, theta, 2, L0=1.0)
+    oracle.ipiano(p, pr.f, bank, theta, 2, L0=1.0)
     t2 = time.perf_counter() - t
     iters = int(max(2, min(60, seconds_target / max(t2 / 2, 1e-3))))
     t = time.perf_counter()
     r = oracle.ipiano(p, pr.f, bank, theta, iters, L0=1.0)
     dt = time.perf_counter() - t
     n_acc = int(r.stats.shape[0])
-    return {"value": round(H * W * n_acc / dt / 1e6, 4), "unit": "Mpixel-iters/s", "cores": oracle.get_threads(),
-            "kind": "oracle",
+    return H * W * n_acc / dt / 1e6, n_acc, int(r.stats[:, 4].sum()), dt
+
+
+def cpu_baseline(pr, bank, theta, seconds_target=15.0):
+    import oracle
+    cores = oracle.get_threads()
+    v, n_acc, trials, dt = _oracle_rate(pr, bank, theta, seconds_target)
+    oracle.set_threads(1)
+    try:
+        v1, n1, _, dt1 = _oracle_rate(pr, bank, theta, seconds_target / 2)
+    finally:
+        oracle.set_threads(cores)
+    return {"value": round(v, 4), "unit": "Mpixel-iters/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, same 512x512 input, first {n_acc} iterations from x0 = log f "
-                      f"({int(r.stats[:, 4].sum())} trials), {dt:.1f} s"}
+                      f"({trials} trials), {dt:.1f} s on {cores} threads",
+            "one_core": {"value": round(v1, 4), "cores": 1, "sample": f"first {n1} iterations, {dt1:.1f} s"},
+            "host_cpu": _cpu_model()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # ------------------------------------------------------------------------------------ forms
@@ -414,29 +440,42 @@ def main():
     t0 = time.perf_counter()
     iters_total = 0
     trials_total = 0
+    loop_ms = 0.0
+    launches = 0
     for k in range(args.steps):
         r = s.solve(f, out=out)
         iters_total += r.summary["iters_done"]
         trials_total += r.summary["total_trials"]
+        ms_k, n_k = s.last_timing()
+        loop_ms += ms_k
+        launches += n_k
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     psnr = synth.psnr(out.cpu().numpy(), pr.clean)
     ssim = foe.ssim(out, torch.from_numpy(pr.clean.astype(np.float32)).to(dev))
     log(f"bench: {dt * 1e3 / args.steps:.3f} ms/step, psnr {psnr:.4f} dB, trials/iter {trials_total / iters_total:.4f}")
 
-    # dominant kernel: the fused trial kernel, mean of per-launch HIP event pairs on the solver stream
-    ms_launch = s.profile_trial(50)
+    # dominant kernel: the fused trial kernel.  Its in-solve launch time is the solver's own HIP event pair
+    # on its stream around the iteration loop (graph-launched trials with the in-kernel line-search
+    # decision, plus the few decide kernels and state pulls between graphs) divided by the trial launches.
+    ms_launch = loop_ms / launches
     flop = FLOP_PER_PX_TRIAL * H * W
     achieved = flop / (ms_launch * 1e-3) / 1e12
+    t_bar = trials_total / iters_total
+    # the per-step form: 4,704 (T + 1) flop per pixel-iteration over the whole step's wall time
+    flop_step = FLOP_PER_PX_TRIAL // 2 * (t_bar + 1.0) * H * W * iters_total / args.steps
     traffic = measured_traffic()
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel": "foe_trial_kernel (forward bank on split-FP16 MFMA with FP32 accumulation, adjoint on "
                           "FP32 VALU)",
-                "ms_per_launch": round(ms_launch, 5), "flop_per_launch": flop,
+                "ms_per_launch": round(ms_launch, 5), "launches_per_step": round(launches / args.steps, 2),
+                "flop_per_launch": flop,
+                "frac_per_step": round(flop_step / (dt / args.steps) / 1e12 / PEAK_FP32_TFLOPS, 4),
                 "frac_mixed_peak": round(achieved / MIXED_PEAK_TFLOPS, 4),
-                "limiter": "VALU issue: the adjoint's FMAs run on the VALU without packed FP32; the forward's "
-                           "matrix-core cycles are a small share (hardware counters in profiles/)",
+                "limiter": "VALU issue in the adjoint (plain FP32 FMAs with VGPR operands, about 2.2 cycles "
+                           "per wave instruction per SIMD) and LDS/VALU in the forward (split-FP16 MFMA operands "
+                           "from LDS, rcp and log per value); stage cycles in profiles/",
                 "mixed_peak_tflops": round(MIXED_PEAK_TFLOPS, 1),
                 "kernel_source_hash": kernel_source_hash()}
     s.close()
@@ -469,7 +508,7 @@ def main():
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpixel-iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (forward bank as split-f16 products)", "data": "synthetic",
         "config": {"workload": "512x512 shapes+cosine image, L=1 speckle, COMBINED model (lambda 160, 0.004), "
                                "48 DCT 7x7 filters, SYMMETRIC boundary, beta 0.8, backtracking, "
                                f"{args.iters} iterations per step" + (", gradient unfused" if args.unfused else ""),

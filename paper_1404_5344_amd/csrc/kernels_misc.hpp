@@ -54,7 +54,7 @@ __device__ __forceinline__ void decide_block(DevState* st, const double* __restr
     if (!s.pending) return;   // nothing ran since the last decision
     s.pending = 0;
   }
-  for (int k = 0; k < 5; ++k) s.sums[k] = tot[k];
+  for (int k = 0; k < PART_COLS; ++k) s.sums[k] = k < 5 ? tot[k] : 0.0;
   if (mode == DECIDE_INIT) {
     s.Fcur = tot[0];
     if (s.input_bad) {

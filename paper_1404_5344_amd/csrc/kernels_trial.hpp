@@ -231,38 +231,26 @@ constexpr int KB16_COPY = 88;               // 176 halves: T[-16 .. 159]
 constexpr int KB16_W = 2 * KB16_COPY;
 
 // The live and own bits (bits 2i and 2i + 1) of the passes i of lane m of wave g0 in the split engine's
-// 2 x 8 patch groups: the same in every chunk, so they are formed once per launch.
+// 2 x 8 patch groups: the same in every chunk, so they are formed once per launch.  Every pass is tested
+// with its own row and column in vector registers (g0 is the wave index taken per lane): a few VALU
+// instructions per pass, where scalar loop code would queue the 16 waves of the workgroup on the one
+// scalar unit of the CU.  Bits of passes past the last group are never read.
 template <int TW, int TH, int GS>
 __device__ __forceinline__ unsigned patch_masks(int g0, int lm, int y0, int x0, int H, int W, bool periodic) {
   constexpr int W3 = TW + 2 * R, H3 = TH + 2 * R, NCB = (W3 + 7) / 8, NG = (H3 / 2) * NCB;
-  static_assert(2 * ((NG + GS - 1) / GS) <= 32 && NCB <= 32, "two bits per pass, one per patch column");
+  constexpr int NPASS = (NG + GS - 1) / GS;
+  static_assert(2 * NPASS <= 32 && NCB <= 32, "two bits per pass");
   const int dy = lm >> 3, dx = lm & 7;
-  // column tests of the lane's NCB columns 8 cb + dx, once; the row tests of a pass take one of the two
-  // rows of its patch row, both tested in scalar registers (g0 and the patch counters are wave-uniform)
-  unsigned colin = 0u, colown = 0u;
-#pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) {
-    const int cc = cb * 8 + dx;
-    colin |= (unsigned)((unsigned)(x0 - R + cc) < (unsigned)W) << cb;
-    colown |= (unsigned)((unsigned)(cc - R) < (unsigned)TW) << cb;
-  }
-  int rp = g0 / NCB, cb = g0 - (g0 / NCB) * NCB;
   unsigned m = 0u;
-  int bit = 0;
-  for (int g = g0; g < NG; g += GS, bit += 2) {
-    const int r0 = 2 * rp;
-    const bool rin0 = (unsigned)(y0 - R + r0) < (unsigned)H, rin1 = (unsigned)(y0 - R + r0 + 1) < (unsigned)H;
-    const bool rown0 = (unsigned)(r0 - R) < (unsigned)TH, rown1 = (unsigned)(r0 + 1 - R) < (unsigned)TH;
-    const bool inimg = (dy ? rin1 : rin0) && ((colin >> cb) & 1u);
-    const bool own = inimg && (dy ? rown1 : rown0) && ((colown >> cb) & 1u);
-    m |= (unsigned)(inimg || periodic) << bit;
-    m |= (unsigned)own << (bit + 1);
-    cb += GS % NCB;
-    rp += GS / NCB;
-    if (cb >= NCB) {
-      cb -= NCB;
-      rp += 1;
-    }
+#pragma unroll
+  for (int i = 0; i < NPASS; ++i) {
+    const int g = g0 + i * GS;
+    const int rp = g / NCB, cb = g - rp * NCB;
+    const int rr = 2 * rp + dy, cc = 8 * cb + dx;
+    const bool inimg = (unsigned)(y0 - R + rr) < (unsigned)H && (unsigned)(x0 - R + cc) < (unsigned)W;
+    const bool own = inimg && (unsigned)(rr - R) < (unsigned)TH && (unsigned)(cc - R) < (unsigned)TW;
+    m |= (unsigned)(inimg || periodic) << (2 * i);
+    m |= (unsigned)own << (2 * i + 1);
   }
   return m;
 }
@@ -542,6 +530,9 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   };
   if constexpr (PREFETCH) fetch_taps(0);
 
+  // split engine: live / own bits of this lane's forward passes, the same in every chunk
+  unsigned pmask = 0u;
+  bool have_pmask = false;
   const float* xc;
   const float* xp = nullptr;
   const float* gc = nullptr;
@@ -559,11 +550,16 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
       if (tid == 0) s_dec = *st;
       double tot[5];
       image_totals(a.part_in, im.tile0, im.ntiles, red, tot);
+      // the other waves form their pass masks while thread 0 decides
+      if constexpr (SPLIT) {
+        pmask = patch_masks<TW, TH, NT / 64>(tid >> 6, tid & 15, y0, x0, H, W, bc == PERIODIC);
+        have_pmask = true;
+      }
       if (tid == 0) {
         const bool writer = (int)blockIdx.x == im.tile0;
         if (s_dec.pending && !s_dec.done) {
 #pragma unroll
-          for (int k = 0; k < 5; ++k) s_dec.sums[k] = tot[k];
+          for (int k = 0; k < PART_COLS; ++k) s_dec.sums[k] = k < 5 ? tot[k] : 0.0;
           decide_step(s_dec, tot, pb, writer ? a.stats + (size_t)td.image * a.stats_rows * STAT_COLS : nullptr);
         }
         s_dec.pending = s_dec.done ? 0 : 1;   // this launch runs the next trial unless the image is done
@@ -779,10 +775,8 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
     }
   }
 
-  // split engine: live / own bits of this lane's forward passes, the same in every chunk
-  unsigned pmask = 0u;
-  if constexpr (SPLIT)   // the wave index is uniform: the patch counters live in scalar registers
-    pmask = patch_masks<TW, TH, NT / 64>(__builtin_amdgcn_readfirstlane(tid >> 6), tid & 15, y0, x0, H, W, bc == PERIODIC);
+  if constexpr (SPLIT)
+    if (!have_pmask) pmask = patch_masks<TW, TH, NT / 64>(tid >> 6, tid & 15, y0, x0, H, W, bc == PERIODIC);
 
   // matrix-core adjoint (ZSPLIT): this wave's filter of each chunk on the NB output blocks of the tile, summed
   // over the chunks in gacc
