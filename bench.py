@@ -45,6 +45,7 @@ NF, KK = 48, 49
 FLOP_PER_PX_TRIAL = 2 * 2 * NF * KK   # forward bank on x+ and adjoint bank, one FMA = 2 flop
 KERNEL_SOURCES = ["common.hpp", "device_math.hpp", "kernels_trial.hpp", "foe_lib.hip"]   # kernels and their launch shapes
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "foe_trial_kernel_512x512_hbm_traffic.md")
+UNFUSED_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "foe_trial_kernel_unfused_512x512_hbm_traffic.md")
 
 
 def log(msg):
@@ -59,14 +60,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the trial kernel from the committed counter summary, or None when
-    the summary is missing or was taken on other kernel sources."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def measured_traffic(path=None, key="HBM bytes per launch"):
+    """HBM bytes per launch (or per trial) from a committed counter summary, or None when the summary
+    is missing or was taken on other kernel sources."""
+    path = path or TRAFFIC_SUMMARY
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_SUMMARY).read()
+    text = open(path).read()
     m_hash = re.search(r"kernel source hash:\s*([0-9a-f]+)", text)
-    m_bytes = re.search(r"HBM bytes per launch:\s*([0-9.eE+]+)", text)
+    m_bytes = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
     if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
         return None
     return float(m_bytes.group(1))
@@ -360,7 +362,8 @@ def form_unfused(dev, steps=5):
         r = s.solve(f)
         out[f"mpix_it_s_{name}"] = round(H * W * r.summary["iters_done"] / t / 1e6, 1)
         out[f"psnr_{name}"] = round(synth.psnr(r.u.cpu().numpy(), pr.clean), 4)
-        ms = s.profile_trial(50)
+        ms_loop, n_trials = s.last_timing()   # in-solve: the solver's event pair around its iteration loop
+        ms = ms_loop / n_trials
         out[f"us_per_trial_{name}"] = round(ms * 1e3, 2)
         if fusion:
             # algorithmic HBM bytes of one unfused trial: forward half reads f, x^n, x^(n-1), grad F(x^n)
@@ -368,8 +371,12 @@ def form_unfused(dev, steps=5):
             # writes grad F(x+) (4)
             bpp = 16 + 4 + 4 * NF + 4 * NF + 4 + 4
             out["algorithmic_bytes_per_px_trial"] = bpp
-            out["hbm_gb_s"] = round(bpp * H * W / (ms * 1e-3) / 1e9, 1)
-            out["hbm_frac_of_8tb_s"] = round(bpp * H * W / (ms * 1e-3) / 8e12, 4)
+            out["hbm_gb_s_algorithmic"] = round(bpp * H * W / (ms * 1e-3) / 1e9, 1)
+            out["hbm_frac_of_8tb_s_algorithmic"] = round(bpp * H * W / (ms * 1e-3) / 8e12, 4)
+            meas = measured_traffic(UNFUSED_TRAFFIC_SUMMARY, "HBM bytes per trial")
+            if meas is not None:
+                out["hbm_gb_s_counters"] = round(meas / (ms * 1e-3) / 1e9, 1)
+                out["hbm_frac_of_8tb_s_counters"] = round(meas / (ms * 1e-3) / 8e12, 4)
         s.close()
     return out
 
@@ -393,7 +400,8 @@ def form_lambertw(dev, steps=5):
         r = s.solve(f)
         out[f"mpix_it_s_{name}"] = round(H * W * r.summary["iters_done"] / t / 1e6, 1)
         out[f"psnr_{name}"] = round(synth.psnr(r.u.cpu().numpy(), pr.clean), 4)
-        out[f"us_per_trial_{name}"] = round(s.profile_trial(50) * 1e3, 2)
+        ms_loop, n_trials = s.last_timing()
+        out[f"us_per_trial_{name}"] = round(ms_loop / n_trials * 1e3, 2)
         s.close()
     return out
 
@@ -408,6 +416,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--unfused", action="store_true",
                     help="time the unfused gradient (z planes through HBM) on the main workload (for profiling)")
+    ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32",
+                    help="bf16: the main workload on the BF16 engine (for profiling; the headline is fp32)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device-to-device copy of this many MiB (a known-size kernel for "
                          "scaling hardware byte counters)")
@@ -427,8 +437,9 @@ def main():
     pr = synth.config2()
     bank, theta = synth.dct_bank(), synth.theta_weights(2)
     H, W = pr.f.shape
+    bf16 = args.precision == "bf16"
     p = foe.default_params(H, W, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=args.iters, looks=1,
-                           fusion=1 if args.unfused else 0)
+                           fusion=1 if args.unfused else 0, precision=1 if bf16 else 0)
     stream = torch.cuda.current_stream()
     s = foe.Solver(p, bank, theta, stream=stream)
     f = torch.from_numpy(pr.f).to(dev)
@@ -468,7 +479,7 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel": "foe_trial_kernel (forward bank on split-FP16 MFMA with FP32 accumulation, adjoint on "
-                          "FP32 VALU)",
+                          + ("BF16 MFMA as a Toeplitz GEMM)" if bf16 else "FP32 VALU)"),
                 "ms_per_launch": round(ms_launch, 5), "launches_per_step": round(launches / args.steps, 2),
                 "flop_per_launch": flop,
                 "frac_per_step": round(flop_step / (dt / args.steps) / 1e12 / PEAK_FP32_TFLOPS, 4),
@@ -480,22 +491,29 @@ def main():
                 "kernel_source_hash": kernel_source_hash()}
     s.close()
     # the same workload on the FP32-operand matrix-core engine
-    p32 = foe.default_params(H, W, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=args.iters, looks=1,
+    fp32_engine = None
+    p32 = None if bf16 else foe.default_params(H, W, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=args.iters, looks=1,
                              fusion=1 if args.unfused else 0, engine=foe.ENGINE_MFMA)
-    s32 = foe.Solver(p32, bank, theta, stream=stream)
-    s32.solve(f, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    it32 = 0
-    for k in range(args.steps):
-        it32 += s32.solve(f, out=out).summary["iters_done"]
-    torch.cuda.synchronize()
-    dt32 = time.perf_counter() - t0
-    fp32_engine = {"value": round(H * W * it32 / dt32 / 1e6, 2), "ms_per_step": round(dt32 * 1e3 / args.steps, 4),
-                   "ms_per_launch": round(s32.profile_trial(50), 5),
-                   "psnr_db": round(synth.psnr(out.cpu().numpy(), pr.clean), 4)}
-    s32.close()
-    log(f"bench: FP32-operand engine {fp32_engine}")
+    if p32 is not None:
+        s32 = foe.Solver(p32, bank, theta, stream=stream)
+        out32 = torch.empty_like(f)
+        s32.solve(f, out=out32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it32 = 0
+        loop32, n32 = 0.0, 0
+        for k in range(args.steps):
+            it32 += s32.solve(f, out=out32).summary["iters_done"]
+            ms_k, n_k = s32.last_timing()
+            loop32 += ms_k
+            n32 += n_k
+        torch.cuda.synchronize()
+        dt32 = time.perf_counter() - t0
+        fp32_engine = {"value": round(H * W * it32 / dt32 / 1e6, 2),
+                       "ms_per_step": round(dt32 * 1e3 / args.steps, 4), "ms_per_launch": round(loop32 / n32, 5),
+                       "psnr_db": round(synth.psnr(out32.cpu().numpy(), pr.clean), 4)}
+        s32.close()
+        log(f"bench: FP32-operand engine {fp32_engine}")
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.ones(n, device=dev)
@@ -508,17 +526,20 @@ def main():
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpixel-iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (forward bank as split-f16 products)", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": ("bf16 (adjoint bank; forward as split-f16 products)" if bf16
+                                                   else "f32 (forward bank as split-f16 products)"), "data": "synthetic",
         "config": {"workload": "512x512 shapes+cosine image, L=1 speckle, COMBINED model (lambda 160, 0.004), "
                                "48 DCT 7x7 filters, SYMMETRIC boundary, beta 0.8, backtracking, "
-                               f"{args.iters} iterations per step" + (", gradient unfused" if args.unfused else ""),
+                               f"{args.iters} iterations per step" + (", gradient unfused" if args.unfused else "")
+                               + (", BF16 engine" if bf16 else ""),
                    "pixels": H * W, "iterations": args.iters, "trials_per_iter": round(trials_total / iters_total, 4),
                    "psnr_db": round(psnr, 4), "ssim": round(ssim, 5),
                    "forward_bank": "split-FP16 MFMA: FP32 operand = FP16 head + FP16 tail / 4096, three exact "
                                    "FP16 products per FP32 product, FP32 accumulation"},
         "roofline": roofline,
-        "fp32_operand_engine": fp32_engine,
     }
+    if fp32_engine is not None:
+        res["fp32_operand_engine"] = fp32_engine
     if not args.no_forms:
         forms = {}
         for name, fn in (("batched", form_batched), ("bf16", form_bf16), ("warm_start", form_warm),
