@@ -77,7 +77,10 @@ typedef struct foe_params {
   int32_t ksize;           /* must be 7 */
   int32_t model;           /* foe_model */
   int32_t boundary;        /* foe_boundary */
-  int32_t precision;       /* foe_precision: arithmetic of the filter-bank contraction */
+  int32_t precision;       /* foe_precision: FP32 = both filter-bank contractions at FP32 accuracy; BF16 =
+                              the adjoint contraction of grad F (Sec. II-C) with z and the adjoint taps
+                              rounded to BF16, FP32 accumulation (the forward, F and the line search
+                              keep FP32 accuracy) */
   int32_t step_mode;       /* foe_step_mode */
   int32_t looks;           /* L >= 1; selects the default (lam1, lam2) of Sec. III-B */
   int32_t max_iters;       /* iterations of foe_solve, >= 0; also the stats capacity */
@@ -90,8 +93,9 @@ typedef struct foe_params {
                               split into an FP16 head and a scaled FP16 tail (about 22 significant bits,
                               exact products, FP32 accumulation; u scaled per tile by a power of two;
                               every |tap| < 16384, else EINVAL); AUTO = MFMA_SPLIT when the taps allow
-                              it, else MFMA.  BF16 precision always runs its own MFMA kernel (AUTO or
-                              MFMA, else EINVAL). */
+                              it, else MFMA.  BF16 precision runs its own kernel (the split-FP16
+                              forward and the adjoint bank on BF16 matrix cores): engine must be AUTO
+                              and every |tap| < 16384, else EINVAL. */
   int32_t fusion;          /* foe_fusion: FUSED keeps the 48 z planes on chip; UNFUSED writes them to
                               HBM between a forward and an adjoint launch (num_filters * pixels
                               extra floats of device memory; same results up to summation order) */
