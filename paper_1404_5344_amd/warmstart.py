@@ -24,7 +24,20 @@ import numpy as np
 
 from . import BatchSolver, WarmStartNet, cnn_init_params, default_params
 
-FALLBACK_RATIO = 1.005      # warm-start energy above this multiple of the plain energy -> fallback
+FALLBACK_TOL = 0.005        # warm-start energy above the plain one by this fraction of |H_plain| -> fallback
+
+
+def needs_fallback(H_warm: float, H_plain: float, tol: float | None = None) -> bool:
+    """The energy test of the warm start: fall back to the plain run when the warm-started energy exceeds the
+    plain run's by more than tol |H_plain|.  The energy is sign-indefinite (the lambda2 term of the data term is
+    negative on bright pixels), so the margin is taken on |H_plain|, not as a ratio."""
+    tol = FALLBACK_TOL if tol is None else tol
+    return H_warm - H_plain > tol * abs(H_plain)
+
+
+def energy_gap(H_warm: float, H_plain: float) -> float:
+    """(H_warm - H_plain) / |H_plain|: positive when the warm start ends at a higher energy."""
+    return (H_warm - H_plain) / abs(H_plain)
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_cnn.npy")
 
 
@@ -127,7 +140,7 @@ def evaluate(net: WarmStartNet, f, looks, bank, theta, iters_warm: int = 40, ite
     records = []
     out = u_warm.clone()
     for i in range(n):
-        fb = s_warm[i]["H"] > FALLBACK_RATIO * s_plain[i]["H"]
+        fb = needs_fallback(s_warm[i]["H"], s_plain[i]["H"])
         if fb:
             out[i] = u_plain[i]
         records.append(dict(H_plain=s_plain[i]["H"], H_short=s_short[i]["H"], H_warm=s_warm[i]["H"], fallback=fb))
@@ -176,7 +189,7 @@ def report(n_images: int, path: str = WEIGHTS, iters_warm: int = 40, iters_plain
                                              iters_plain)
     ps = lambda u: np.array([synth.psnr(u[i].cpu().numpy(), clean[i]) for i in range(n_images)])
     p_plain, p_short, p_warm = ps(u_plain), ps(u_short), ps(u_warm)
-    gap = np.array([r["H_warm"] / r["H_plain"] - 1.0 for r in rec])
+    gap = np.array([energy_gap(r["H_warm"], r["H_plain"]) for r in rec])
     out = dict(images=n_images, iters_warm=iters_warm, iters_plain=iters_plain,
                psnr_noisy=float(np.mean([synth.psnr(f_np[i], clean[i]) for i in range(n_images)])),
                psnr_plain=float(p_plain.mean()), psnr_same_iters_from_log_f=float(p_short.mean()),

@@ -63,7 +63,7 @@ def test_shipped_network_on_held_out_images():
     p_plain, p_short, p_warm = _psnrs(u_plain, clean), _psnrs(u_short, clean), _psnrs(u_warm, clean)
     for i in range(n):
         print(f"image {i}: plain 300 {p_plain[i]:.3f} dB, 40 from log f {p_short[i]:.3f}, "
-              f"network + 40 {p_warm[i]:.3f}; energy gap {rec[i]['H_warm'] / rec[i]['H_plain'] - 1:.2e}")
+              f"network + 40 {p_warm[i]:.3f}; energy gap {ws.energy_gap(rec[i]['H_warm'], rec[i]['H_plain']):.2e}")
     assert not any(r["fallback"] for r in rec)
     assert np.all(p_warm >= p_plain - 0.01)
     assert np.mean(p_warm) > np.mean(p_short)
@@ -76,8 +76,8 @@ def test_fallback_takes_the_plain_result(monkeypatch):
     f_np, clean, looks = ws.held_out(2, workers=1)
     f = torch.from_numpy(f_np[:, :128, :128].copy()).to(dev)
     net = ws.load()
-    # a ratio below 1 sends every image whose warm energy is not below the plain one to the fallback
-    monkeypatch.setattr(ws, "FALLBACK_RATIO", 0.5)
+    # a tolerance of -inf sends every image to the fallback
+    monkeypatch.setattr(ws, "FALLBACK_TOL", float("-inf"))
     u_plain, _, u_out, rec = ws.evaluate(net, f, looks, synth.dct_bank(), synth.theta_weights(5), 5, 20)
     assert all(r["fallback"] for r in rec)
     assert torch.equal(u_out, u_plain)
