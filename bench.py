@@ -264,6 +264,7 @@ def form_batched(dev, n_images=64):
         return lambda: b.solve_from(f, prep.x, prep.xp, [1.0] * n_images, k)
     t_batch = _wall_prepped(prep, run_batch(K))
     t_batch300 = _wall_prepped(prep, run_batch(300), reps=2)
+    lat = b.latency()   # per-image, device timestamps, of the last 300-iteration batch run
     # one solver per image, run one after the other
     singles = []
     for i, (H, W) in enumerate(hw):
@@ -293,6 +294,9 @@ def form_batched(dev, n_images=64):
             "mpix_it_s_batched": round(total_px * 300 / t_batch300 / 1e6, 1),
             "mpix_it_s_one_by_one": round(total_px * 300 / t_seq300 / 1e6, 1),
             "latency_s_batched_all_images": round(t_batch300, 4),
+            "latency_ms_per_image_device": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                            "p95": round(float(np.percentile(lat, 95)), 3),
+                                            "max": round(float(lat.max()), 3), "min": round(float(lat.min()), 3)},
             "latency_s_one_by_one_mean_image": round(t_seq300 / n_images, 5)}
 
 
@@ -403,6 +407,61 @@ def form_lambertw(dev, steps=5):
         ms_loop, n_trials = s.last_timing()
         out[f"us_per_trial_{name}"] = round(ms_loop / n_trials * 1e3, 2)
         s.close()
+    return out
+
+
+def form_context(dev):
+    """The run-time experiment of Sec. III-D: L = 8 images of 512x512, 481x321 and 256x256, lambda = (550, 0.02),
+    300 iterations on the GPU, beside the paper's GTX 680 times (its iteration count unstated: context only).
+    The FP64 oracle's times on the same images are in cpu_baseline.context."""
+    import torch
+    import paper_1404_5344_amd as foe
+    import synth
+    paper_s = {(512, 512): 0.6, (321, 481): 0.41, (256, 256): 0.2}
+    bank, theta = synth.dct_bank(), synth.theta_weights(7)
+    out = {"workload": "shapes+cosine images at L=8, lambda (550, 0.02), DCT bank, 300 iterations"}
+    for (H, W) in synth.CONTEXT_SIZES:
+        pr = synth.context_image(H, W)
+        p = foe.default_params(H, W, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=300, looks=8)
+        s = foe.Solver(p, bank, theta)
+        f = torch.from_numpy(pr.f).to(dev)
+        cfg = s.autotune(f, reps=5)   # the tile shape for this size (32 x 16 fills more CUs on small images)
+        r = s.solve(f)
+        t = _wall(lambda: s.solve(f), reps=5)
+        n_it = r.summary["iters_done"]
+        out[f"{W}x{H}"] = {"gpu_ms_per_solve": round(t * 1e3, 3), "gpu_mpix_it_s": round(H * W * n_it / t / 1e6, 1),
+                           "tile": "32x32" if cfg == 0 else "32x16",
+                           "psnr_noisy": round(synth.psnr(pr.f, pr.clean), 4),
+                           "psnr_gpu": round(synth.psnr(r.u.cpu().numpy(), pr.clean), 4),
+                           "paper_gtx680_s_per_solve": paper_s[(H, W)]}
+        s.close()
+    return out
+
+
+def cpu_context():
+    """The FP64 oracle on the Sec. III-D images (cpu_baseline leg): a bounded sample of iterations on all host
+    cores and on one core, scaled to Mpixel-it/s and to seconds per 300 iterations."""
+    import oracle
+    import synth
+    bank, theta = synth.dct_bank(), synth.theta_weights(7)
+    cores = oracle.get_threads()
+    out = {}
+    for (H, W) in synth.CONTEXT_SIZES:
+        pr = synth.context_image(H, W)
+        po = oracle.Params(lam1=pr.lam1, lam2=pr.lam2)
+        rec = {}
+        for label, nthreads, iters in (("all_cores", cores, 2), ("one_core", 1, 1)):
+            oracle.set_threads(nthreads)
+            try:
+                t0 = time.perf_counter()
+                ro = oracle.ipiano(po, pr.f, bank, theta, iters, L0=1.0)
+                dt = time.perf_counter() - t0
+            finally:
+                oracle.set_threads(cores)
+            n = max(int(ro.stats.shape[0]), 1)
+            rec[f"{label}_mpix_it_s"] = round(H * W * n / dt / 1e6, 4)
+            rec[f"{label}_s_per_300_iterations"] = round(dt / n * 300, 1)
+        out[f"{W}x{H}"] = rec
     return out
 
 
@@ -543,7 +602,7 @@ def main():
     if not args.no_forms:
         forms = {}
         for name, fn in (("batched", form_batched), ("bf16", form_bf16), ("warm_start", form_warm),
-                         ("unfused", form_unfused), ("lambertw", form_lambertw)):
+                         ("unfused", form_unfused), ("lambertw", form_lambertw), ("context", form_context)):
             t = time.perf_counter()
             log(f"bench: form {name}")
             forms[name] = fn(dev)
@@ -552,6 +611,8 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
         res["cpu_baseline"] = cpu_baseline(pr, bank, theta)
+        if not args.no_forms:
+            res["cpu_baseline"]["context"] = cpu_context()
     print(json.dumps(res), flush=True)
 
 

@@ -176,8 +176,9 @@ foe_status foe_batch_solve(foe_solver* s, const float* d_f, const float* d_init,
 /* ---- Tile-shape autotuner.  Times `reps` fused trial launches of each tile configuration
  * (32x32, 32x16 output tiles) on the solver's images with input d_f (packed), keeps the
  * fastest, and records it in the file named by the environment variable FOE_TUNE_CACHE
- * (when set; keyed by engine, boundary, filter count and the sorted image sizes) so later
- * solvers with the same key skip the timing.  *chosen receives the configuration index.
+ * (when set; keyed by engine, boundary, filter count, fusion and the size bucket: the count of
+ * 32 x 32 tiles of all images rounded up to a power of two, single image or batch) so later
+ * solvers in the same bucket skip the timing.  *chosen receives the configuration index.
  * Results do not depend on the configuration beyond floating-point summation order. */
 foe_status foe_autotune(foe_solver* s, const float* d_f, int32_t reps, int32_t* chosen);
 foe_status foe_set_tile_config(foe_solver* s, int32_t cfg);
@@ -211,6 +212,19 @@ foe_status foe_eval_prox(foe_solver* s, const float* d_xhat, const float* d_f, d
  * info_host (nullable, 4 doubles) = {F(x+), G(x+), <grad F(x), d>, |d|^2}. */
 foe_status foe_step(foe_solver* s, const float* d_f, const float* d_x, const float* d_xprev, double L_forced,
                     float* d_xnext, double* info_host);
+
+/* Per-image latency of the last foe_solve / foe_solve_from / foe_batch_solve, from device timestamps:
+ * ms_host[i] (caller array of n_images doubles) = time from the start of the iterations (the decision on
+ * the gradient at x^0) to the decision that completed image i (its last accepted trial; taken at the
+ * start of the next launch, so within one launch of the image's last write), in milliseconds of the
+ * device's wall clock; -1 for an image that did not complete.  Images of a batch that finish early stop
+ * computing while the others continue, so the latencies differ per image.  Errors: EINVAL, EDEVICE. */
+foe_status foe_batch_latency(foe_solver* s, double* ms_host);
+
+/* Parameters of the real-SAR experiment (Sec. III-C: an L = 5 image, lambda1 = 50, lambda2 = 0.15), on
+ * top of foe_default_params (the looks table would give the interpolated 406, 0.0128 for L = 5);
+ * height and width are 0 (the caller sets them).  Errors: EINVAL (p NULL). */
+foe_status foe_real_sar_params(foe_params* p);
 
 /* Kernel time of the last foe_solve / foe_solve_from in milliseconds (HIP events on the
  * solver stream around the iteration loop), and the number of fused trial launches. */

@@ -70,6 +70,8 @@ def _load():
     L.foe_eval_prox.argtypes = [_VP, _VP, _VP, ctypes.c_double, _VP]
     L.foe_step.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _DP]
     L.foe_last_timing.argtypes = [_VP, _DP, ctypes.POINTER(ctypes.c_int32)]
+    L.foe_batch_latency.argtypes = [_VP, _DP]
+    L.foe_real_sar_params.argtypes = [ctypes.POINTER(Params)]
     L.foe_profile_trial.argtypes = [_VP, ctypes.c_int32, _DP]
     _IP = ctypes.POINTER(ctypes.c_int32)
     L.foe_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, _IP, _IP, _DP, _DP, _IP, _VP, _VP, _VP,
@@ -97,7 +99,8 @@ def _load():
     for name in ("foe_create", "foe_destroy", "foe_solve", "foe_solve_from", "foe_eval_gradient", "foe_eval_energy",
                  "foe_eval_prox", "foe_step", "foe_last_timing", "foe_profile_trial", "foe_batch_create",
                  "foe_batch_layout", "foe_batch_solve", "foe_autotune", "foe_solve_noalloc", "foe_set_tile_config", "foe_cnn_create",
-                 "foe_cnn_destroy", "foe_cnn_get_params", "foe_cnn_infer", "foe_cnn_loss_grad", "foe_cnn_train_step"):
+                 "foe_cnn_destroy", "foe_cnn_get_params", "foe_cnn_infer", "foe_cnn_loss_grad", "foe_cnn_train_step",
+                 "foe_batch_latency", "foe_real_sar_params"):
         getattr(L, name).restype = ctypes.c_int
     if L.foe_abi_version() != ABI_VERSION:
         raise ImportError(f"{LIB_PATH} has ABI version {L.foe_abi_version()}, this binding expects {ABI_VERSION}")
@@ -115,6 +118,18 @@ def _check(st: int, allow=(OK,)):
     if st not in allow:
         raise FoeError(st, lib.foe_last_error().decode())
     return st
+
+
+def real_sar_params(height: int, width: int, **kw) -> Params:
+    """The parameters of the real-SAR experiment (Sec. III-C: L = 5, lambda = (50, 0.15)), see foe_real_sar_params."""
+    p = Params()
+    _check(lib.foe_real_sar_params(ctypes.byref(p)))
+    p.height, p.width = int(height), int(width)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
 
 
 def default_params(height: int, width: int, **kw) -> Params:
@@ -270,6 +285,12 @@ class Solver:
         n = ctypes.c_int32()
         _check(lib.foe_last_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def latency(self) -> np.ndarray:
+        """Per-image latency (ms) of the last solve from device timestamps (see foe_batch_latency)."""
+        out = np.zeros(getattr(self, "n_images", 1))
+        _check(lib.foe_batch_latency(self._h, out.ctypes.data_as(_DP)))
+        return out
 
 
 def solve_noalloc(params: Params, filters, weights, f, init=None, out=None, stream=None,

@@ -35,6 +35,8 @@ struct DevState {
   int done;                // 1 => every later trial / decide launch is a no-op
   int input_bad;           // set by the init kernel when f or u0 is invalid
   int pending;             // 1 => a trial has run whose partials await the decision
+  long long t_start;       // device wall clock when the solve's initial state was written
+  long long t_done;        // device wall clock of the decision that completed the image (0 while running)
 };
 
 // One image of a (possibly single-image) batch: packed-plane offset, size, data-term weights and

@@ -10,7 +10,7 @@ namespace foe {
 // non-finite F(x+) or G(x+) fails; on acceptance rotate the x and gradient rings and write the stats row
 // (row: the image's stats, or null to skip the write); on rejection L <- eta_up L.  FIXED mode always
 // accepts.
-__device__ __forceinline__ void decide_step(DevState& s, const double (&tot)[5], const Problem& pb, double* row) {
+__device__ __forceinline__ void decide_step_core(DevState& s, const double (&tot)[5], const Problem& pb, double* row) {
   const double F = tot[0], G = tot[1], s1 = tot[2], s2 = tot[3], m = tot[4];
   s.trials += 1;
   s.total_trials += 1;
@@ -49,6 +49,13 @@ __device__ __forceinline__ void decide_step(DevState& s, const double (&tot)[5],
     s.L = pb.eta_up * L;
     s.alpha = 1.9 * (1.0 - pb.beta_d) / s.L;
   }
+}
+
+// The decision, with the device wall-clock time at which it completes the image (per-image latency).
+__device__ __forceinline__ void decide_step(DevState& s, const double (&tot)[5], const Problem& pb, double* row) {
+  const int was_done = s.done;
+  decide_step_core(s, tot, pb, row);
+  if (s.done && !was_done) s.t_done = (long long)wall_clock64();
 }
 
 // One step of wave_sum_f64: v + (v moved by the DPP pattern CTRL; 0 where the pattern has no source

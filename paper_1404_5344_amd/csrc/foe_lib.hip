@@ -639,14 +639,17 @@ foe_status init_from_f(foe_solver* s, const float* d_f, const float* d_u0, bool*
   return FOE_OK;
 }
 
-// Key of the autotuner cache: engine and the sorted image sizes.
+// Key of the autotuner cache: engine, boundary, filter count, fusion, and the size bucket of the work: the
+// number of 32 x 32 tiles of all images, rounded up to a power of two (the tile shapes differ in how well
+// they fill the 256 CUs, which that count decides), and whether the batch holds one image or several.
 std::string tune_key(const foe_solver* s) {
-  std::vector<std::pair<int, int>> sz;
-  for (const ImageDesc& im : s->images) sz.push_back({im.H, im.W});
-  std::sort(sz.begin(), sz.end());
+  long long tiles = 0;
+  for (const ImageDesc& im : s->images) tiles += (long long)((im.H + 31) / 32) * ((im.W + 31) / 32);
+  int b = 0;
+  while ((1ll << b) < tiles) ++b;
   std::ostringstream o;
-  o << "e" << s->pb.engine << "_bc" << s->pb.bc << "_nf" << s->pb.nf;
-  for (auto& q : sz) o << "_" << q.first << "x" << q.second;
+  o << "e" << s->pb.engine << "_bc" << s->pb.bc << "_nf" << s->pb.nf << "_u" << (s->zbuf ? 1 : 0) << "_t2^" << b
+    << (s->n_img > 1 ? "_batch" : "_single");
   return o.str();
 }
 
@@ -842,6 +845,28 @@ foe_status foe_last_timing(foe_solver* s, double* ms, int32_t* trial_launches) {
   if (!s) return fail(FOE_EINVAL, "solver is NULL");
   if (ms) *ms = s->last_ms;
   if (trial_launches) *trial_launches = s->last_launches;
+  return FOE_OK;
+}
+
+foe_status foe_batch_latency(foe_solver* s, double* ms_host) {
+  if (!s || !ms_host) return fail(FOE_EINVAL, "NULL argument");
+  int dev = 0, khz = 0;
+  HIP_OR(hipGetDevice(&dev));
+  HIP_OR(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) return fail(FOE_EDEVICE, "the device reports no wall-clock rate");
+  for (int i = 0; i < s->n_img; ++i) {
+    const DevState& h = s->st_host[i];
+    ms_host[i] = h.t_done > 0 && h.t_start > 0 ? (double)(h.t_done - h.t_start) / (double)khz : -1.0;
+  }
+  return FOE_OK;
+}
+
+foe_status foe_real_sar_params(foe_params* p) {
+  if (!p) return fail(FOE_EINVAL, "NULL argument");
+  foe_default_params(p);
+  p->looks = 5;
+  p->lambda1 = 50.0;
+  p->lambda2 = 0.15;
   return FOE_OK;
 }
 

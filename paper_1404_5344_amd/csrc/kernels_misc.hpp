@@ -56,6 +56,8 @@ __device__ __forceinline__ void decide_block(DevState* st, const double* __restr
   }
   for (int k = 0; k < PART_COLS; ++k) s.sums[k] = k < 5 ? tot[k] : 0.0;
   if (mode == DECIDE_INIT) {
+    s.t_start = (long long)wall_clock64();   // the iterations start now (per-image latency)
+    s.t_done = 0;
     s.Fcur = tot[0];
     if (s.input_bad) {
       s.status = ST_EINPUT;

@@ -265,3 +265,31 @@ def config5_eval(index: int, H: int = 512, W: int = 512, looks: int = 1) -> Prob
     f = speckle(clean, looks, 50, index)
     l1, l2 = default_lambdas(looks)
     return Problem(clean, f, looks, l1, l2, 255.0)
+
+
+# ---------------------------------------------------------------- presets of the paper's other experiments
+# The real-SAR experiment (Sec. III-C): an L = 5 image despeckled with lambda1 = 50, lambda2 = 0.15.  The
+# JSTARS image is not available; a SAR-like GRF image with point targets stands in for it.
+SAR_PRESET_LOOKS = 5
+SAR_PRESET_LAMBDA = (50.0, 0.15)
+
+
+def sar_preset(index: int = 0, H: int = 256, W: int = 256) -> Problem:
+    """SAR-like image (GRF with point targets, config id 6) under L = 5 speckle, with the real-SAR
+    lambdas of Sec. III-C; PSNR peak = max(clean)."""
+    clean = grf_sar_image(6, index, H, W)
+    f = speckle(clean, SAR_PRESET_LOOKS, 6, index)
+    return Problem(clean, f, SAR_PRESET_LOOKS, SAR_PRESET_LAMBDA[0], SAR_PRESET_LAMBDA[1], float(clean.max()))
+
+
+# The run-time experiment (Sec. III-D): L = 8 images of 512 x 512, 481 x 321 and 256 x 256 (the combined
+# model with lambda1 = 550, lambda2 = 0.02, the L = 8 values of Sec. III-B).
+CONTEXT_SIZES = ((512, 512), (321, 481), (256, 256))   # (H, W): 481 x 321 as 481 wide
+
+
+def context_image(H: int, W: int, index: int = 0) -> Problem:
+    """Shapes + cosine image (config id 7) of the given size under L = 8 speckle, lambda = (550, 0.02)."""
+    clean = shapes_cosine_image(7, index, H, W)
+    f = speckle(clean, 8, 7, index)
+    l1, l2 = default_lambdas(8)
+    return Problem(clean, f, 8, l1, l2, 255.0)

@@ -75,3 +75,15 @@ def test_noalloc_rejects_oversized_images_before_any_device_call():
     assert st == foe.EINVAL and b"fused" in foe.lib.foe_last_error()
     p = foe.default_params(64, 64)
     assert foe.lib.foe_solve_noalloc(ctypes.byref(p), k, th, None, None, None, dummy, None, None) == foe.EINVAL
+
+
+def test_real_sar_preset_params():
+    """Sec. III-C: the real SAR image has L = 5 looks and is despeckled with lambda1 = 50, lambda2 = 0.15
+    (the looks table would interpolate other values for L = 5)."""
+    import paper_1404_5344_amd as foe
+    p = foe.real_sar_params(128, 96)
+    assert (p.height, p.width, p.looks) == (128, 96, 5)
+    assert p.lambda1 == 50.0 and p.lambda2 == 0.15
+    assert p.num_filters == 48 and p.beta == 0.8 and p.model == 0
+    assert foe.lib.foe_real_sar_params(None) == foe.EINVAL
+    assert foe.lib.foe_batch_latency(None, None) == foe.EINVAL

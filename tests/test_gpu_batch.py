@@ -94,8 +94,23 @@ def test_autotuner_and_tile_configs(tmp_path):
             res[cfg] = out.cpu().numpy()
         assert np.max(np.abs(res[0] - res[1]) / res[0]) <= 1e-5
         bf.close()
-        # a second tuner call hits the cache
+        # a second tuner call hits the cache, and so does another batch in the same size bucket (other
+        # sizes, the same count of 32 x 32 tiles up to a power of two): no new cache line
         assert b.autotune(f, reps=2) == c
+        sizes2 = SIZES[:-1] + [(120, 64)]
+        probs2 = [synth.config3_image(i, H, W, L) for i, ((H, W), L) in enumerate(zip(sizes2, LOOKS))]
+        b2 = foe.BatchSolver(p, sizes2, LOOKS, bank, theta)
+        f2 = b2.pack([torch.from_numpy(pr.f) for pr in probs2]).to(dev)
+        assert b2.autotune(f2, reps=2) == c
+        assert len((tmp_path / "tune.txt").read_text().strip().splitlines()) == 1
+        b2.close()
+        # a single image is a bucket of its own
+        s1 = make_solver(64, 96, bank, theta, max_iters=20)
+        c1 = s1.autotune(torch.from_numpy(probs[0].f).to(dev), reps=2)
+        assert c1 in (0, 1)
+        lines = (tmp_path / "tune.txt").read_text().strip().splitlines()
+        assert len(lines) == 2 and "_single" in lines[1] and "_batch" in lines[0]
+        s1.close()
         b.close()
     finally:
         del os.environ["FOE_TUNE_CACHE"]
@@ -128,3 +143,33 @@ def test_uneven_batch_against_stored_oracle_runs():
         assert sums[i]["iters_done"] == 300
         assert d <= 0.05, (i, d)
     b.close()
+
+
+def test_per_image_latency_from_device_timestamps():
+    """foe_batch_latency: every image of a batch completes after a positive time and no later than the whole
+    iteration loop (the solver's event pair around it, with a little slack), the last one after at least half
+    of it; a single-image solve reports about its loop time."""
+    import paper_1404_5344_amd as foe
+    torch, dev = torch_dev()
+    probs = _problems()
+    bank, theta = synth.dct_bank(), synth.theta_weights(3)
+    p = foe.default_params(0, 0, max_iters=60)
+    b = foe.BatchSolver(p, SIZES, LOOKS, bank, theta)
+    f = b.pack([torch.from_numpy(pr.f) for pr in probs]).to(dev)
+    b.solve(f)
+    lat = b.latency()
+    loop_ms, launches = b.last_timing()
+    print("latency ms per image:", np.round(lat, 4), "loop", round(loop_ms, 4), "ms over", launches, "launches")
+    assert lat.shape == (len(SIZES),)
+    assert np.all(lat > 0.0)
+    assert np.all(lat <= loop_ms * 1.05 + 0.1)
+    assert lat.max() >= 0.5 * loop_ms
+    b.close()
+    pr = probs[1]
+    s = make_solver(pr.f.shape[0], pr.f.shape[1], bank, theta, max_iters=60, looks=pr.looks)
+    s.solve(torch.from_numpy(pr.f).to(dev))
+    (one,) = s.latency()
+    loop_ms, _ = s.last_timing()
+    print("single image latency", one, "loop", loop_ms)
+    assert 0.5 * loop_ms <= one <= loop_ms * 1.05 + 0.1
+    s.close()
