@@ -50,14 +50,19 @@ foe_status fail(foe_status st, const std::string& msg) {
 // Tile configurations of the fused kernel (chosen per solver, by the autotuner if asked).
 // V_NT threads per workgroup; the FP32 and split-FP16 matrix-core engines run V_NT_MFMA (16 waves: four per
 // SIMD hide the LDS and matrix-pipe latencies better, and their registers fit in the 128 VGPRs that allows).
-constexpr int V_NC = 16, V_NT = 512, V_NT_MFMA = 1024, V_BR = 4, V_BC = 2;
-// adjoint block width of the matrix-core kernels: 4 x 4 output blocks on 32 x 32 tiles
+constexpr int V_NC = 16, V_NT = 512, V_NT_MFMA = 1024, V_BC = 2;
+// adjoint register blocks: 4 x 4 outputs on 32 x 32 tiles of the matrix-core kernels, 4 x 2 on 32 x 16 tiles,
+// 2 x 2 on 32 x 8 tiles (a filter group is a whole number of waves: (TH / BR) (TW / BC) = 64 threads)
+constexpr int br_for(int th) { return th == 8 ? 2 : 4; }
 constexpr int bc_mfma(int th) { return th == 32 ? 4 : V_BC; }
 struct TileCfg {
   int tw, th;
 };
-constexpr TileCfg TILE_CFGS[2] = {{32, 32}, {32, 16}};
-constexpr int N_TILE_CFGS = 2;
+// 32 x 8 tiles spread small images over more CUs (a 256 x 256 image is 64 tiles of 32 x 32 but 256 of 32 x 8);
+// the BF16 engine's z strips take 16-row blocks, so it runs the first two only
+constexpr TileCfg TILE_CFGS[3] = {{32, 32}, {32, 16}, {32, 8}};
+constexpr int N_TILE_CFGS = 3;
+constexpr bool cfg_ok(int cfg, int engine) { return !(TILE_CFGS[cfg].th % 16 != 0 && engine == 2 /* FWD_MFMA_BF16 */); }
 constexpr int GRAPH_BIG = 16;
 static_assert(GRAPH_BIG % 2 == 0, "a big graph must return the state to parity 0");
 
@@ -240,14 +245,17 @@ FusedArgs fused_args(foe_solver* s, int mode, const float* f, const float* x_in,
 
 template <int TW, int TH, int UNF>
 void launch_engine(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
-  if (s->pb.engine == FWD_MFMA_BF16)
-    foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_BF16, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
-  else if (s->pb.engine == FWD_MFMA_F32)
-    foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_F32, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
-  else if (s->pb.engine == FWD_MFMA_F16X)
-    foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_F16X, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
-  else
-    foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
+  constexpr int BR = br_for(TH);
+  if (s->pb.engine == FWD_MFMA_BF16) {
+    if constexpr (TH % 16 == 0)   // cfg_ok keeps the BF16 engine off other tile heights
+      foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, BR, bc_mfma(TH), FWD_MFMA_BF16, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
+  } else if (s->pb.engine == FWD_MFMA_F32) {
+    foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, BR, bc_mfma(TH), FWD_MFMA_F32, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
+  } else if (s->pb.engine == FWD_MFMA_F16X) {
+    foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, BR, bc_mfma(TH), FWD_MFMA_F16X, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
+  } else {
+    foe_trial_kernel<TW, TH, V_NC, V_NT, BR, V_BC, FWD_VALU, UNF><<<s->nblocks, V_NT, 0, stream>>>(a);
+  }
 }
 
 // One trial (or evaluation): the fused kernel, or its two halves exchanging z through HBM.
@@ -257,19 +265,24 @@ void launch_cfg(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
     launch_engine<TW, TH, FWD_HALF>(s, a, stream);
     // the adjoint half runs no forward bank; it takes the adjoint form and thread count of the engine's fused
     // kernel, so that both paths compute the adjoint with the same arithmetic in the same order
-    if (s->pb.engine == FWD_MFMA_BF16)
-      foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_MFMA_BF16, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
-    else if (s->pb.engine == FWD_MFMA_F32 || s->pb.engine == FWD_MFMA_F16X)
-      foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, V_BR, bc_mfma(TH), FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
-    else
-      foe_trial_kernel<TW, TH, V_NC, V_NT, V_BR, V_BC, FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT, 0, stream>>>(a);
+    constexpr int BR = br_for(TH);
+    if (s->pb.engine == FWD_MFMA_BF16) {
+      if constexpr (TH % 16 == 0)
+        foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, BR, bc_mfma(TH), FWD_MFMA_BF16, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
+    } else if (s->pb.engine == FWD_MFMA_F32 || s->pb.engine == FWD_MFMA_F16X) {
+      foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, BR, bc_mfma(TH), FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
+    } else {
+      foe_trial_kernel<TW, TH, V_NC, V_NT, BR, V_BC, FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT, 0, stream>>>(a);
+    }
   } else {
     launch_engine<TW, TH, FUSED>(s, a, stream);
   }
 }
 
 void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
-  if (s->tile_cfg == 1)
+  if (s->tile_cfg == 2)
+    launch_cfg<32, 8>(s, a, stream);
+  else if (s->tile_cfg == 1)
     launch_cfg<32, 16>(s, a, stream);
   else
     launch_cfg<32, 32>(s, a, stream);
@@ -916,7 +929,7 @@ foe_status foe_autotune(foe_solver* s, const float* d_f, int32_t reps, int32_t* 
     std::string k;
     int c;
     while (in >> k >> c)
-      if (k == key && c >= 0 && c < N_TILE_CFGS) best = c;
+      if (k == key && c >= 0 && c < N_TILE_CFGS && cfg_ok(c, s->pb.engine)) best = c;
   }
   if (best < 0) {
     bool bad = false;
@@ -928,6 +941,7 @@ foe_status foe_autotune(foe_solver* s, const float* d_f, int32_t reps, int32_t* 
     HIP_OR(hipEventCreate(&e0));
     HIP_OR(hipEventCreate(&e1));
     for (int c = 0; c < N_TILE_CFGS; ++c) {
+      if (!cfg_ok(c, s->pb.engine)) continue;
       build_tiles(s, c);
       st = upload_tiles(s);
       if (st != FOE_OK) return st;
@@ -962,6 +976,7 @@ foe_status foe_autotune(foe_solver* s, const float* d_f, int32_t reps, int32_t* 
 
 foe_status foe_set_tile_config(foe_solver* s, int32_t cfg) {
   if (!s || cfg < 0 || cfg >= N_TILE_CFGS) return fail(FOE_EINVAL, "bad tile configuration");
+  if (!cfg_ok(cfg, s->pb.engine)) return fail(FOE_EINVAL, "the BF16 engine takes 32 x 32 and 32 x 16 tiles only");
   HIP_OR(hipStreamSynchronize(s->stream));
   drop_graphs(s);
   build_tiles(s, cfg);

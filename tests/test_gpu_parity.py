@@ -127,11 +127,11 @@ def test_random_filters_and_filter_counts(nf, engine):
     s.close()
 
 
-@pytest.mark.parametrize("cfg", [0, 1])
+@pytest.mark.parametrize("cfg", [0, 1, 2])
 @pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("shape", [(37, 64), (70, 45), (100, 131), (33, 257), (66, 98), (17, 18)])
 def test_gradient_tile_configs(shape, bc, cfg):
-    """Both tile configurations (32x32 and 32x16 output tiles) against the oracle."""
+    """Every tile configuration (32x32, 32x16 and 32x8 output tiles) against the oracle."""
     torch, dev = torch_dev()
     H, W = shape
     clean, f = speckled(H, W, seed=H * 7 + W)

@@ -167,9 +167,10 @@ def test_determinism_and_resume():
     s.close()
 
 
-@pytest.mark.parametrize("shape,cfg", [((1024, 1056), 0), ((640, 600), 1)])
+@pytest.mark.parametrize("shape,cfg", [((1024, 1056), 0), ((640, 600), 1), ((300, 200), 2)])
 def test_resume_bitwise_on_images_of_many_tiles(shape, cfg):
-    """Images of more than 256 tiles (1024 x 1056: 1056 tiles of 32 x 32; 640 x 600: 760 tiles of 32 x 16): the
+    """Images of more than 256 tiles (1024 x 1056: 1056 tiles of 32 x 32; 640 x 600: 760 tiles of 32 x 16;
+    300 x 200: 266 tiles of 32 x 8): the
     in-kernel decision and the decide kernel reduce the partials in the same order, so 2 x 30 iterations from
     the same state give the same bits as 60."""
     torch, dev = torch_dev()
