@@ -148,15 +148,28 @@ def _crossing(traj, target):
     return int(hit[0]) if hit.size else None
 
 
-def _probe(solver, f, x0, clean_t, peak, iters, exp=True):
-    """PSNR after 0..iters iterations from x^0 = x^{-1} = x0 (single-image solver)."""
+def _probe(solver, f, x0, clean_t, peak, iters, exp=True, energy=None):
+    """PSNR after 0..iters iterations from x^0 = x^{-1} = x0 (single-image solver); with energy (a solver
+    of FP32 accuracy on the same problem) also the energy H = F + G of every iterate."""
     import torch
     x, xp, L = x0.clone(), x0.clone(), 1.0
     out = [_psnr_t(torch.exp(x) if exp else x, clean_t, peak)]
+    hs = [sum(energy.eval_energy(x, f))] if energy is not None else None
     for _ in range(iters):
         L, _, _ = solver.solve_from(f, x, xp, L, 1)
         out.append(_psnr_t(torch.exp(x), clean_t, peak))
-    return out
+        if energy is not None:
+            hs.append(sum(energy.eval_energy(x, f)))
+    return out if energy is None else (out, hs)
+
+
+ENERGY_TOL = 0.005   # time-to-energy: H within 0.5 % of the plain solve's final H
+
+
+def _energy_crossing(hs, h_ref):
+    """First iteration whose energy is within ENERGY_TOL of h_ref (relative to abs(h_ref)), or None."""
+    hit = np.nonzero(np.asarray(hs) - h_ref <= ENERGY_TOL * abs(h_ref))[0]
+    return int(hit[0]) if hit.size else None
 
 
 def _run_from(solver, f, x0, k):
@@ -196,15 +209,16 @@ def form_bf16(dev):
     f = torch.from_numpy(pr.f).to(dev)
     clean = torch.from_numpy(pr.clean).to(dev)
     x0 = torch.log(f)
-    res = {}
+    res, hs = {}, {}
     solvers = {}
     for name, kw in (("fp32", {}), ("bf16", dict(precision=1))):
         p = foe.default_params(2048, 2048, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=300, **kw)
         solvers[name] = foe.Solver(p, bank, theta)
-        res[name] = _probe(solvers[name], f, x0, clean, pr.peak, 300)
+        res[name], hs[name] = _probe(solvers[name], f, x0, clean, pr.peak, 300, energy=solvers.get("fp32", solvers[name]))
     target = res["fp32"][-1] - 0.05
     out = {"workload": "2048x2048 SAR-like tile 0, L=1, 300 iterations", "tol_db": 0.05,
-           "psnr_final_fp32": round(res["fp32"][-1], 4), "psnr_final_bf16": round(res["bf16"][-1], 4)}
+           "psnr_final_fp32": round(res["fp32"][-1], 4), "psnr_final_bf16": round(res["bf16"][-1], 4),
+           "energy_tol_rel": ENERGY_TOL, "H_final_fp32": hs["fp32"][-1], "H_final_bf16": hs["bf16"][-1]}
     for name in ("fp32", "bf16"):
         k = _crossing(res[name], target)
         out[f"reached_{name}"] = k is not None
@@ -212,11 +226,20 @@ def form_bf16(dev):
         prep, run = _run_from(solvers[name], f, x0, k)
         out[f"iters_{name}"] = k
         out[f"seconds_{name}"] = round(_wall_prepped(prep, run), 5)
+        # time to energy: the first iterate whose H (FP32-accuracy evaluation) is within 0.5 % of the
+        # FP32 solve's final H
+        ke = _energy_crossing(hs[name], hs["fp32"][-1])
+        out[f"energy_reached_{name}"] = ke is not None
+        ke = 300 if ke is None else ke
+        prep, run = _run_from(solvers[name], f, x0, ke)
+        out[f"energy_iters_{name}"] = ke
+        out[f"energy_seconds_{name}"] = round(_wall_prepped(prep, run), 5)
         # throughput of the full 300 iterations in this precision
         prep, run = _run_from(solvers[name], f, x0, 300)
         t300 = _wall_prepped(prep, run, reps=2)
         out[f"mpix_it_s_{name}"] = round(2048 * 2048 * 300 / t300 / 1e6, 1)
     out["speedup"] = round(out["seconds_fp32"] / out["seconds_bf16"], 3)
+    out["energy_speedup"] = round(out["energy_seconds_fp32"] / out["energy_seconds_bf16"], 3)
     for s in solvers.values():
         s.close()
     return out
@@ -314,9 +337,12 @@ def form_warm(dev):
     net = ws.load()
     x0 = torch.log(f)
     u0 = net.infer(f.reshape(1, 512, 512)).reshape(512, 512)
-    plain = _probe(s, f, x0, clean, 255.0, 300)
-    warm = _probe(s, f, torch.log(u0), clean, 255.0, 40)
+    plain, h_plain = _probe(s, f, x0, clean, 255.0, 300, energy=s)
+    warm, h_warm = _probe(s, f, torch.log(u0), clean, 255.0, 40, energy=s)
     target = plain[-1] - 0.01
+    # time to energy: the first iterate with H within 0.5 % of the plain final H
+    ke_plain = _energy_crossing(h_plain, h_plain[-1])
+    ke_warm = _energy_crossing(h_warm, h_plain[-1])
     k_plain = _crossing(plain, target)
     k_plain = 300 if k_plain is None else k_plain
     k_warm = _crossing(warm, target)
@@ -338,13 +364,29 @@ def form_warm(dev):
         fallback = True
     t_warm = _wall(run_w)
     t_net = _wall(lambda: net.infer(f3))
+    energy = {"energy_tol_rel": ENERGY_TOL, "H_final_plain": h_plain[-1], "H_network_only": h_warm[0],
+              "H_network_plus_40": h_warm[-1], "energy_iters_plain": ke_plain, "energy_iters_warm": ke_warm}
+    prep, run = _run_from(s, f, x0, ke_plain)
+    te_plain = _wall_prepped(prep, run)
+    energy["energy_seconds_plain"] = round(te_plain, 5)
+    if ke_warm is not None:
+        def run_we():
+            w = torch.log(net.infer(f3).reshape(512, 512))
+            if ke_warm > 0:
+                s.solve_from(f, w, w.clone(), 1.0, ke_warm)
+        te_warm = _wall(run_we)
+        energy["energy_seconds_warm"] = round(te_warm, 5)
+        energy["energy_speedup"] = round(te_plain / te_warm, 3)
+    else:
+        energy["energy_seconds_warm"] = None   # not reached in 40 iterations: the fallback would run
+        energy["energy_speedup"] = None
     net.close()
     s.close()
     return {"workload": "held-out 512x512 image, L=1; network + up to 40 iterations vs plain 300", "tol_db": 0.01,
             "psnr_final_plain": round(plain[-1], 4), "psnr_network_only": round(warm[0], 4),
             "psnr_network_plus_40": round(warm[-1], 4), "iters_plain": k_plain, "iters_warm": k_warm,
             "fallback": fallback, "seconds_plain": round(t_plain, 5), "seconds_warm": round(t_warm, 5),
-            "seconds_network": round(t_net, 5), "speedup": round(t_plain / t_warm, 3)}
+            "seconds_network": round(t_net, 5), "speedup": round(t_plain / t_warm, 3), **energy}
 
 
 def form_unfused(dev, steps=5):

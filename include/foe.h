@@ -92,8 +92,10 @@ typedef struct foe_params {
                               GEMM on FP16 matrix cores (v_mfma_f32_16x16x32_f16), each FP32 operand
                               split into an FP16 head and a scaled FP16 tail (about 22 significant bits,
                               exact products, FP32 accumulation; u scaled per tile by a power of two;
-                              every |tap| < 16384, else EINVAL); AUTO = MFMA_SPLIT when the taps allow
-                              it, else MFMA.  BF16 precision runs its own kernel (the split-FP16
+                              every |tap| < 16384, else EINVAL; a tap is carried to an absolute 2^-36,
+                              so a filter whose largest |tap| is below 2^-10 loses relative accuracy);
+                              AUTO = MFMA_SPLIT when every |tap| < 16384 and every nonzero filter has a
+                              largest |tap| of at least 2^-10, else MFMA.  BF16 precision runs its own kernel (the split-FP16
                               forward and the adjoint bank on BF16 matrix cores): engine must be AUTO
                               and every |tap| < 16384, else EINVAL. */
   int32_t fusion;          /* foe_fusion: FUSED keeps the 48 z planes on chip; UNFUSED writes them to
@@ -243,11 +245,13 @@ foe_status foe_profile_trial(foe_solver* s, int32_t reps, double* ms_mean);
  * from u0 = e^{w0} (foe_solve's d_init).  Parameters: per layer the weights
  * W[co][ci][3][3] followed by the biases b[co], layers in order, foe_cnn_num_params() floats
  * in total.  The handle keeps FP32 master parameters and their BF16 rounding; every
- * convolution uses the BF16-rounded values with FP32 activations and accumulation.
- * Batches are n images of one size H x W, packed [n][H][W] in device memory.  Activation
- * workspace (13 planes of 32 n H W floats at most) is allocated on the first call of a larger
- * size and kept.  Calls synchronise the handle's stream before returning.
- * Errors: EINVAL (NULL or non-positive sizes), ENOMEM, EDEVICE. */
+ * convolution uses the BF16-rounded values with FP32 activations and accumulation (the four
+ * 32 -> 32 layers, forward, backward-data and backward-weight, on the BF16 matrix cores with every
+ * FP32 activation or gradient split into three BF16 parts: FP32 accuracy).
+ * Batches are n images of one size H x W (H W < 2^25), packed [n][H][W] in device memory.
+ * Activation workspace (13 planes of 32 n H W floats at most) is allocated on the first call of a
+ * larger size and kept.  Calls synchronise the handle's stream before returning.
+ * Errors: EINVAL (NULL or non-positive sizes, H W >= 2^25), ENOMEM, EDEVICE. */
 typedef struct foe_cnn foe_cnn;
 int64_t foe_cnn_num_params(void);
 /* params_host: foe_cnn_num_params() floats, copied; Adam moments start at zero. */

@@ -83,6 +83,10 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 // Largest |tap| the split-FP16 engine takes: the heads stay below 2^14 and the 4096-scaled tails
 // below 2^15, inside the FP16 range.
 constexpr float SPLIT_MAX_TAP = 16384.0f;
+// The split carries a tap to an absolute resolution of 2^-36 (a head below 2^-14 is an FP16 subnormal):
+// relative to a filter whose largest |tap| is at least 2^-10 that is below 2^-26.  AUTO takes the FP32
+// engine for a bank with a smaller nonzero filter.
+constexpr float SPLIT_MIN_FILTER_MAX = 1.0f / 1024.0f;
 
 // The split-FP16 operands of the forward taps kf ([chunk][t][j], t = 7 a + b): per chunk and lane
 // (m = lane % 16, k = lane / 16), for steps s = 0, 1, the heads then the 4096-scaled tails of tap
@@ -332,10 +336,15 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
     if (!(std::isfinite(p->eta_up) && p->eta_up > 1.0)) return fail(FOE_EINVAL, "eta_up must be > 1");
     if (!(p->eta_down > 0.0 && p->eta_down <= 1.0)) return fail(FOE_EINVAL, "eta_down must be in (0, 1]");
   }
-  bool split_ok = true;
+  bool split_ok = true, split_fine = true;
   for (int i = 0; i < p->num_filters * FOE_KSIZE * FOE_KSIZE; ++i) {
     if (!std::isfinite(filters[i])) return fail(FOE_EINVAL, "non-finite filter tap");
     if (!(std::fabs(filters[i]) < SPLIT_MAX_TAP)) split_ok = false;
+  }
+  for (int j = 0; j < p->num_filters; ++j) {
+    float mx = 0.0f;
+    for (int t = 0; t < FOE_KSIZE * FOE_KSIZE; ++t) mx = std::max(mx, std::fabs(filters[j * FOE_KSIZE * FOE_KSIZE + t]));
+    if (mx > 0.0f && mx < SPLIT_MIN_FILTER_MAX) split_fine = false;
   }
   if ((p->engine == FOE_ENGINE_MFMA_SPLIT || p->precision == FOE_PREC_BF16) && !split_ok)
     return fail(FOE_EINVAL, "the split-FP16 engine (also the forward of BF16 precision) takes taps with |k| < 16384");
@@ -359,8 +368,10 @@ foe_status validate(const foe_params* p, const float* filters, const float* weig
     pb->engine = FWD_VALU;
   else if (p->engine == FOE_ENGINE_MFMA)
     pb->engine = FWD_MFMA_F32;
-  else   // MFMA_SPLIT, or AUTO: the split engine unless a tap is out of its range
-    pb->engine = split_ok ? FWD_MFMA_F16X : FWD_MFMA_F32;
+  else if (p->engine == FOE_ENGINE_MFMA_SPLIT)
+    pb->engine = FWD_MFMA_F16X;
+  else   // AUTO: the split engine unless a tap is out of its range or a filter is below its resolution
+    pb->engine = split_ok && split_fine ? FWD_MFMA_F16X : FWD_MFMA_F32;
   return FOE_OK;
 }
 

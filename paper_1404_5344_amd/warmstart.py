@@ -201,8 +201,37 @@ def report(n_images: int, path: str = WEIGHTS, iters_warm: int = 40, iters_plain
     return out
 
 
+def time_kernels(reps: int = 20):
+    """Wall time of the shipped network's inference on one 512 x 512 image and of one loss-and-gradient
+    evaluation on a batch of 32 images of 128 x 128 (medians over reps calls, inputs resident)."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    net = load()
+    g = torch.Generator(device="cpu").manual_seed(0)
+    f = (torch.rand(1, 512, 512, generator=g) * 200 + 1).to(dev)
+    fb = (torch.rand(32, 128, 128, generator=g) * 200 + 1).to(dev)
+    ut = fb * 1.1
+    out = {}
+    for name, fn in (("infer_512x512_ms", lambda: net.infer(f)), ("loss_grad_32x128x128_ms", lambda: net.loss_grad(fb, ut))):
+        for _ in range(3):
+            fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        out[name] = round(float(np.median(ts)) * 1e3, 4)
+        print(name, out[name], flush=True)
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--time", action="store_true", help="time the network's inference and gradient kernels")
     ap.add_argument("--evaluate", type=int, default=0, help="evaluate the saved network on this many held-out images")
     ap.add_argument("--images", type=int, default=20000)
     ap.add_argument("--epochs", type=int, default=8)
@@ -211,6 +240,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=WEIGHTS)
     a = ap.parse_args()
+    if a.time:
+        time_kernels()
+        return
     if a.evaluate:
         report(a.evaluate, a.out)
         return

@@ -221,3 +221,27 @@ def test_auto_engine_is_the_split_engine():
         out[engine] = (s.eval_gradient(_gpu(x, dev)).cpu().numpy(), s.eval_energy(_gpu(x, dev), _gpu(f, dev)))
         s.close()
     assert np.array_equal(out[0][0], out[3][0]) and out[0][1] == out[3][1]
+
+
+def test_auto_engine_falls_back_for_tiny_filters():
+    """The split carries a tap to an absolute 2^-36, so AUTO runs a bank with a nonzero filter whose
+    largest abs(tap) is below 2^-10 on the FP32-operand engine: bitwise that engine's gradient and
+    energies, and the gradient within the FP32 bar of the oracle on a bank scaled by 2^-18 (theta scaled
+    by 2^36 to keep the gradient of order one)."""
+    torch, dev = torch_dev()
+    H, W = 37, 64
+    clean, f = speckled(H, W, seed=13)
+    bank, theta = bank_and_theta("random", seed=5)
+    bank = (np.asarray(bank, np.float64) * 2.0 ** -18).astype(np.float32)
+    theta = (np.asarray(theta, np.float64) * 2.0 ** 36).astype(np.float32)
+    assert 0.0 < np.abs(bank).max() < 2.0 ** -10
+    x = state_for(oracle.COMBINED, f)
+    g_ora = oracle.grad_F(x, bank, theta, oracle.COMBINED, oracle.SYMMETRIC)
+    out = {}
+    for engine in (0, 2, 3):   # AUTO, FP32 operands, split FP16
+        s = make_solver(H, W, bank, theta, engine=engine)
+        out[engine] = (s.eval_gradient(_gpu(x, dev)).cpu().numpy(), s.eval_energy(_gpu(x, dev), _gpu(f, dev)))
+        s.close()
+    print("gradient rel err: FP32 engine %.3e, split engine %.3e" % (rel_inf(out[2][0], g_ora), rel_inf(out[3][0], g_ora)))
+    assert np.array_equal(out[0][0], out[2][0]) and out[0][1] == out[2][1]
+    assert rel_inf(out[0][0], g_ora) <= 1e-4
