@@ -487,10 +487,18 @@ foe_status status_of(int st) {
 
 // Runs the iteration loop of every image from ring slots 0 / 1; fbuf holds f.  Summaries and
 // stats are per image.  Returns the first image's failure status, if any.
-foe_status run_loop(foe_solver* s, const double* L_in, int iters, foe_summary* sums, double* stats_host) {
+// The iteration loop from the ring state (x^0 in slot 0, x^{-1} in slot 1).  pre (nullable) is launched on
+// the stream after the state upload and before the evaluation at x^0: the input check, which sets
+// input_bad; then the first state download, which the loop needs anyway, also reports the check (the
+// decision at x^0 marks such an image done), and the call returns EINPUT without iterating.  Each round
+// launches the trials still missing plus a few more (at least GRAPH_BIG), so that rejected trials seldom
+// cost a second round (a trial launch after an image is done leaves it unchanged).
+template <class Pre>
+foe_status run_loop(foe_solver* s, const double* L_in, int iters, foe_summary* sums, double* stats_host, Pre pre) {
   reset_states(s, L_in, iters);
   foe_status e = push_states(s);
   if (e != FOE_OK) return e;
+  pre();
   // F, G and grad F at x^0
   launch_fused(s, fused_args(s, MODE_EVAL, s->fbuf, s->xr[0], s->gr[0]), s->stream);
   launch_decide(s, DECIDE_INIT, s->stream);
@@ -506,9 +514,14 @@ foe_status run_loop(foe_solver* s, const double* L_in, int iters, foe_summary* s
   HIP_OR(hipEventRecord(s->ev0, s->stream));
   e = pull_states(s);
   if (e != FOE_OK) return e;
+  bool bad = false;
+  for (int i = 0; i < s->n_img; ++i) bad = bad || s->st_host[i].input_bad;
+  if (bad) {
+    if (sums) std::memset(sums, 0, sizeof(foe_summary) * s->n_img);
+    return fail(FOE_EINPUT, "f or the initial image has a non-finite or non-positive pixel");
+  }
   std::vector<double> G0(s->n_img);
   for (int i = 0; i < s->n_img; ++i) G0[i] = s->st_host[i].sums[1];
-  int launches = 0;
   for (;;) {
     int remaining = 0;
     for (int i = 0; i < s->n_img; ++i) {
@@ -516,17 +529,19 @@ foe_status run_loop(foe_solver* s, const double* L_in, int iters, foe_summary* s
       if (!h.done) remaining = std::max(remaining, h.target - h.iter);
     }
     if (remaining <= 0) break;
+    // at least one big graph: a short solve from a far L0 (ten or more rejections in its first iteration)
+    // still ends in one round
+    const int n_launch = std::max(GRAPH_BIG, remaining + remaining / 16 + 1);
     // the state and partials start at parity 0; GRAPH_BIG is even, so each big graph ends at parity 0
     int q = 0;
-    for (int k = 0; k < remaining / GRAPH_BIG; ++k) HIP_OR(hipGraphLaunch(s->graph_big, s->stream));
-    for (int k = 0; k < remaining % GRAPH_BIG; ++k) {
+    for (int k = 0; k < n_launch / GRAPH_BIG; ++k) HIP_OR(hipGraphLaunch(s->graph_big, s->stream));
+    for (int k = 0; k < n_launch % GRAPH_BIG; ++k) {
       HIP_OR(hipGraphLaunch(q ? s->graph_one1 : s->graph_one, s->stream));
       q ^= 1;
     }
     // the decision on the last trial, then the state back to parity 0
     launch_decide(s, DECIDE_STEP, s->stream, q);
     if (q) HIP_OR(hipMemcpyAsync(s->st, s->st2, sizeof(DevState) * s->n_img, hipMemcpyDeviceToDevice, s->stream));
-    launches += remaining;
     e = pull_states(s);
     if (e != FOE_OK) return e;
   }
@@ -535,6 +550,9 @@ foe_status run_loop(foe_solver* s, const double* L_in, int iters, foe_summary* s
   float ms = 0.f;
   HIP_OR(hipEventElapsedTime(&ms, s->ev0, s->ev1));
   s->last_ms = ms;
+  // launches that ran a trial: one per trial of the image with the most trials (the others are no-ops)
+  int launches = 0;
+  for (int i = 0; i < s->n_img; ++i) launches = std::max(launches, s->st_host[i].total_trials);
   s->last_launches = launches;
   std::vector<double> rows;
   if (stats_host || sums) {
@@ -749,16 +767,13 @@ foe_status foe_destroy(foe_solver* s) {
 foe_status foe_batch_solve(foe_solver* s, const float* d_f, const float* d_init, float* d_u_out,
                            foe_summary* sums_host, double* stats_host) {
   if (!s || !d_f || !d_u_out) return fail(FOE_EINVAL, "NULL argument");
-  bool bad = false;
-  foe_status st = init_from_f(s, d_f, d_init, &bad);
-  if (st != FOE_OK) return st;
-  if (bad) {
-    st = fail(FOE_EINPUT, "f or the initial image has a non-finite or non-positive pixel");
-    if (sums_host) std::memset(sums_host, 0, sizeof(foe_summary) * s->n_img);
-  } else {
-    std::vector<double> L(s->n_img, s->p.L0);
-    st = run_loop(s, L.data(), s->p.max_iters, sums_host, stats_host);
-  }
+  HIP_OR(hipMemcpyAsync(s->fbuf, d_f, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
+  std::vector<double> L(s->n_img, s->p.L0);
+  // ring slot 0 = x^0 (from f or d_init) even if the input is rejected
+  foe_status st = run_loop(s, L.data(), s->p.max_iters, sums_host, stats_host, [&] {
+    init_state_kernel<<<grid_img(s), 256, 0, s->stream>>>(s->fbuf, d_init, s->xr[0], s->xr[1], s->d_images,
+                                                          s->pb.model, s->st);
+  });
   finalize_kernel<<<grid_img(s), 256, 0, s->stream>>>(s->st, s->xr[0], s->xr[1], s->xr[2], d_u_out, s->d_images,
                                                       s->pb.model);
   HIP_OR(hipGetLastError());
@@ -781,16 +796,10 @@ foe_status foe_solve_from(foe_solver* s, const float* d_f, float* d_x_cur, float
   HIP_OR(hipMemcpyAsync(s->fbuf, d_f, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
   HIP_OR(hipMemcpyAsync(s->xr[0], d_x_cur, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
   HIP_OR(hipMemcpyAsync(s->xr[1], d_x_prev, sizeof(float) * s->n, hipMemcpyDeviceToDevice, s->stream));
-  reset_states(s, L_inout, iters);
-  foe_status e = push_states(s);
-  if (e != FOE_OK) return e;
-  check_input_kernel<<<grid_img(s), 256, 0, s->stream>>>(s->fbuf, s->d_images, s->st);
-  HIP_OR(hipGetLastError());
-  e = pull_states(s);
-  if (e != FOE_OK) return e;
-  for (int i = 0; i < s->n_img; ++i)
-    if (s->st_host[i].input_bad) return fail(FOE_EINPUT, "f has a non-finite or non-positive pixel");
-  foe_status st = run_loop(s, L_inout, iters, sum_host, stats_host);
+  foe_status st = run_loop(s, L_inout, iters, sum_host, stats_host, [&] {
+    check_input_kernel<<<grid_img(s), 256, 0, s->stream>>>(s->fbuf, s->d_images, s->st);
+  });
+  if (st == FOE_EINPUT) return st;   // the state is left as it was
   export_state_kernel<<<grid_img(s), 256, 0, s->stream>>>(s->st, s->xr[0], s->xr[1], s->xr[2], d_x_cur, d_x_prev,
                                                           s->d_images);
   HIP_OR(hipGetLastError());
