@@ -614,6 +614,10 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
         u6[(i + 2 * R) * W6 + jx + 2 * R] = logm ? fast_exp(xn) : xn;
       }
     }
+    // the halves after the last strip, which no chunk writes, read by the matrix-core adjoint's last rows
+    // (k >= 154) against zero taps: zeros, as in the fused kernel
+    if constexpr (ZSPLIT)
+      if (tid < 4) reinterpret_cast<unsigned*>(zp)[NC * ZS::FILTER_H / 2 + tid] = 0u;
   } else {
     // the positions of this thread, two at a time: their loads first (invalid positions read pixel 0
     // and are discarded), so that the HBM latency of the block's inputs is paid once per batch
