@@ -53,6 +53,16 @@ struct TileDesc {
   int image, x0, y0, pad;
 };
 
+// The tile (row-major index over the image's n tiles) of the image's i-th block.  Workgroups are dealt to
+// the 8 XCDs in turn (block b on XCD b % 8); the blocks of one residue class i % 8 take consecutive tiles,
+// so that neighbouring tiles, which read each other's halo lines, meet in one L2 (exactly so for an image
+// whose first block is a multiple of 8, as in every single-image solve).  The order depends on n alone,
+// so an image runs the same tile order, and sums its partials in the same order, alone or in a batch.
+__host__ __device__ inline int xcd_tile_order(int i, int n) {
+  const int c = i % 8, r = i / 8, q = n / 8, rem = n % 8;   // classes c < rem hold q + 1 blocks, the others q
+  return c * q + (c < rem ? c : rem) + r;
+}
+
 // Solver-wide constants (shared by every image of a batch).
 struct Problem {
   int H, W;

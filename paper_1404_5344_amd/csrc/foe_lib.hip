@@ -205,9 +205,12 @@ void build_tiles(foe_solver* s, int cfg) {
   for (int i = 0; i < s->n_img; ++i) {
     ImageDesc& im = s->images[i];
     im.tile0 = (int)s->tiles.size();
-    for (int y = 0; y < im.H; y += tc.th)
-      for (int x = 0; x < im.W; x += tc.tw) s->tiles.push_back(TileDesc{i, x, y, 0});
-    im.ntiles = (int)s->tiles.size() - im.tile0;
+    const int ntx = (im.W + tc.tw - 1) / tc.tw, n = ntx * ((im.H + tc.th - 1) / tc.th);
+    for (int b = 0; b < n; ++b) {
+      const int t = xcd_tile_order(b, n);
+      s->tiles.push_back(TileDesc{i, (t % ntx) * tc.tw, (t / ntx) * tc.th, 0});
+    }
+    im.ntiles = n;
   }
   s->tile_cfg = cfg;
   s->nblocks = (int)s->tiles.size();

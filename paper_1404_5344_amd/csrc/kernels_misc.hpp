@@ -111,8 +111,10 @@ __global__ void export_state_kernel(const DevState* states, const float* x0, con
 // The tile list of one image in row-major tile order (the order build_tiles gives on the host):
 // tile t = (image 0, x0 = (t % ntx) tw, y0 = (t / ntx) th).
 __global__ void tile_list_kernel(TileDesc* tiles, int ntx, int ntiles, int tw, int th) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x)
-    tiles[t] = TileDesc{0, (t % ntx) * tw, (t / ntx) * th, 0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ntiles; i += gridDim.x * blockDim.x) {
+    const int t = xcd_tile_order(i, ntiles);
+    tiles[i] = TileDesc{0, (t % ntx) * tw, (t / ntx) * th, 0};
+  }
 }
 
 __global__ void prox_probe_kernel(const float* __restrict__ xh, const float* __restrict__ f, float* out, size_t n,
