@@ -176,8 +176,8 @@ foe_status foe_batch_solve(foe_solver* s, const float* d_f, const float* d_init,
                            foe_summary* sums_host, double* stats_host);
 
 /* ---- Tile-shape autotuner.  Times `reps` fused trial launches of each tile configuration
- * (0: 32x32, 1: 32x16, 2: 32x8 output tiles; the BF16 engine takes 0 and 1 only, foe_set_tile_config
- * returns EINVAL for the others) on the solver's images with input d_f (packed), keeps the
+ * (0: 32x32, 1: 32x16, 2: 32x8, 3: 64x8 output tiles; the BF16 engine takes 0 and 1 only,
+ * foe_set_tile_config returns EINVAL for the others) on the solver's images with input d_f (packed), keeps the
  * fastest, and records it in the file named by the environment variable FOE_TUNE_CACHE
  * (when set; keyed by engine, boundary, filter count, fusion and the size bucket: the count of
  * 32 x 32 tiles of all images rounded up to a power of two, single image or batch) so later

@@ -52,17 +52,22 @@ foe_status fail(foe_status st, const std::string& msg) {
 // SIMD hide the LDS and matrix-pipe latencies better, and their registers fit in the 128 VGPRs that allows).
 constexpr int V_NC = 16, V_NT = 512, V_NT_MFMA = 1024, V_BC = 2;
 // adjoint register blocks: 4 x 4 outputs on 32 x 32 tiles of the matrix-core kernels, 4 x 2 on 32 x 16 tiles,
-// 2 x 2 on 32 x 8 tiles (a filter group is a whole number of waves: (TH / BR) (TW / BC) = 64 threads)
+// 2 x 2 on 32 x 8 and 64 x 8 tiles (a filter group is a whole number of waves: (TH / BR) (TW / BC) = 64 or 128
+// threads)
 constexpr int br_for(int th) { return th == 8 ? 2 : 4; }
 constexpr int bc_mfma(int th) { return th == 32 ? 4 : V_BC; }
 struct TileCfg {
   int tw, th;
 };
 // 32 x 8 tiles spread small images over more CUs (a 256 x 256 image is 64 tiles of 32 x 32 but 256 of 32 x 8);
-// the BF16 engine's z strips take 16-row blocks, so it runs the first two only
-constexpr TileCfg TILE_CFGS[3] = {{32, 32}, {32, 16}, {32, 8}};
-constexpr int N_TILE_CFGS = 3;
-constexpr bool cfg_ok(int cfg, int engine) { return !(TILE_CFGS[cfg].th % 16 != 0 && engine == 2 /* FWD_MFMA_BF16 */); }
+// 64 x 8 tiles, half as many, carry less halo per output (76 x 20 / (64 x 8) = 2.97 against 44 x 20 / (32 x 8)
+// = 3.44 for 32 x 8).  The BF16 engine's z strips take 32-column tiles of 16-row blocks, so it runs the first
+// two only
+constexpr TileCfg TILE_CFGS[4] = {{32, 32}, {32, 16}, {32, 8}, {64, 8}};
+constexpr int N_TILE_CFGS = 4;
+constexpr bool cfg_ok(int cfg, int engine) {
+  return !((TILE_CFGS[cfg].th % 16 != 0 || TILE_CFGS[cfg].tw != 32) && engine == 2 /* FWD_MFMA_BF16 */);
+}
 constexpr int GRAPH_BIG = 16;
 static_assert(GRAPH_BIG % 2 == 0, "a big graph must return the state to parity 0");
 
@@ -254,7 +259,7 @@ template <int TW, int TH, int UNF>
 void launch_engine(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
   constexpr int BR = br_for(TH);
   if (s->pb.engine == FWD_MFMA_BF16) {
-    if constexpr (TH % 16 == 0)   // cfg_ok keeps the BF16 engine off other tile heights
+    if constexpr (TH % 16 == 0 && TW == 32)   // cfg_ok keeps the BF16 engine off other tile shapes
       foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, BR, bc_mfma(TH), FWD_MFMA_BF16, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
   } else if (s->pb.engine == FWD_MFMA_F32) {
     foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, BR, bc_mfma(TH), FWD_MFMA_F32, UNF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
@@ -274,7 +279,7 @@ void launch_cfg(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
     // kernel, so that both paths compute the adjoint with the same arithmetic in the same order
     constexpr int BR = br_for(TH);
     if (s->pb.engine == FWD_MFMA_BF16) {
-      if constexpr (TH % 16 == 0)
+      if constexpr (TH % 16 == 0 && TW == 32)
         foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, BR, bc_mfma(TH), FWD_MFMA_BF16, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
     } else if (s->pb.engine == FWD_MFMA_F32 || s->pb.engine == FWD_MFMA_F16X) {
       foe_trial_kernel<TW, TH, V_NC, V_NT_MFMA, BR, bc_mfma(TH), FWD_VALU, ADJ_HALF><<<s->nblocks, V_NT_MFMA, 0, stream>>>(a);
@@ -287,7 +292,9 @@ void launch_cfg(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
 }
 
 void launch_fused(foe_solver* s, const FusedArgs& a, hipStream_t stream) {
-  if (s->tile_cfg == 2)
+  if (s->tile_cfg == 3)
+    launch_cfg<64, 8>(s, a, stream);
+  else if (s->tile_cfg == 2)
     launch_cfg<32, 8>(s, a, stream);
   else if (s->tile_cfg == 1)
     launch_cfg<32, 16>(s, a, stream);

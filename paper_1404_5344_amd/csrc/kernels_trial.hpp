@@ -400,7 +400,7 @@ __device__ __forceinline__ float mfma_forward_chunk(const float* u6, const unsig
     const unsigned* b = u16 + (cc & 1) * SP::COPY1 + (rr + lk) * SP::ROW_W + (cc >> 1);
     float* zq = zp + rr * ZW + cc;
     // ZSPLIT: strip 0 takes the columns < 22, strip 1 the columns 16 .. W3 - 1 (never the padding columns)
-    constexpr int SW = 22, SH = ZSPLIT ? ZStrips<TW, ZSPLIT ? TH : 16>::STRIP_H : 0;
+    constexpr int SW = 22, SH = ZSPLIT ? ZStrips<ZSPLIT ? TW : 32, ZSPLIT ? TH : 16>::STRIP_H : 0;
     constexpr int DZH = DR * SW + DC, DZH_WRAP = (DR + 2) * SW + DC - 8 * NCB;
     __bf16* zh0 = reinterpret_cast<__bf16*>(zp) + rr * SW + cc;
     __bf16* zh1 = zh0 + SH - 16;
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
   // the BF16 engine's fused kernel and adjoint half: z as BF16 strips, the adjoint bank on the matrix cores
   // (ZStrips)
   constexpr bool ZSPLIT = FWD == FWD_MFMA_BF16 && (UNF == FUSED || UNF == ADJ_HALF);
-  using ZS = ZStrips<TW, ZSPLIT ? TH : 16>;   // only the BF16 engine's strips (16-row blocks) are ever used
+  using ZS = ZStrips<ZSPLIT ? TW : 32, ZSPLIT ? TH : 16>;   // only the BF16 engine's strips are ever used
   constexpr int ZS_WORDS = (NC * ZS::FILTER_H + 8) / 2;   // strips of the chunk + the zero padding
   constexpr int ZP_FLOATS = ZSPLIT ? (ZS_WORDS > NG * TH * TW ? ZS_WORDS : NG * TH * TW) : NC * PLANE;
   static_assert(NG * TH * TW <= ZP_FLOATS, "epilogue does not fit in the z buffer");

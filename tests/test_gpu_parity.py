@@ -127,7 +127,7 @@ def test_random_filters_and_filter_counts(nf, engine):
     s.close()
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
 @pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("shape", [(37, 64), (70, 45), (100, 131), (33, 257), (66, 98), (17, 18)])
 def test_gradient_tile_configs(shape, bc, cfg):

@@ -167,7 +167,7 @@ def test_determinism_and_resume():
     s.close()
 
 
-@pytest.mark.parametrize("shape,cfg", [((1024, 1056), 0), ((640, 600), 1), ((300, 200), 2)])
+@pytest.mark.parametrize("shape,cfg", [((1024, 1056), 0), ((640, 600), 1), ((300, 200), 2), ((300, 530), 3)])
 def test_resume_bitwise_on_images_of_many_tiles(shape, cfg):
     """Images of more than 256 tiles (1024 x 1056: 1056 tiles of 32 x 32; 640 x 600: 760 tiles of 32 x 16;
     300 x 200: 266 tiles of 32 x 8): the

@@ -6,7 +6,7 @@ and the epilogue's reuse of the z buffer as the group sums.
 The index expressions restate those of paper_1404_5344_amd/csrc/kernels_trial.hpp (z_row_stride,
 z_plane_stride, the forwards' z stores, the adjoint's zb / wrow reads, fold_block and ZLines, the fold item
 decoding and slot layout, the epilogue's add(slot, d) calls, gsum) with the launch shapes of foe_lib.hip
-(32 x 32 / 32 x 16 / 32 x 8 tiles, 1024 threads on the matrix-core engines and 512 on the VALU engine).  For
+(32 x 32 / 32 x 16 / 32 x 8 / 64 x 8 tiles, 1024 threads on the matrix-core engines and 512 on the VALU engine).  For
 every tile of several images (corner, edge, ragged and interior tiles, images 4 and 5 pixels wide), the
 emulation asserts that every LDS access lies inside the buffer the kernel declares, that every z value read
 was written in the chunk and is not a padding column, that each fold partial has one writer per chunk, and
@@ -285,11 +285,14 @@ CASES = [  # (tile height, forward engine, image sizes)
     (16, FWD_MFMA_F16X, [(35, 38), (5, 4)]),
     (8, FWD_MFMA_F16X, [(19, 35)]),
 ]
+CASES_64 = [  # 64 x 8 tiles
+    (8, FWD_MFMA_F16X, [(19, 70), (4, 5)]),
+    (8, FWD_VALU, [(9, 67)]),
+]
 
 
-@pytest.mark.parametrize("TH,fwd,sizes", CASES)
-def test_fp32_planes_fold_and_epilogue(TH, fwd, sizes):
-    TW = 32
+@pytest.mark.parametrize("TW,TH,fwd,sizes", [(32,) + c for c in CASES] + [(64,) + c for c in CASES_64])
+def test_fp32_planes_fold_and_epilogue(TW, TH, fwd, sizes):
     rng = np.random.default_rng(TH * 10 + fwd)
     for H, W in sizes:
         z_img = rng.uniform(-0.5, 0.5, size=(NC, H, W))
