@@ -46,6 +46,7 @@ FLOP_PER_PX_TRIAL = 2 * 2 * NF * KK   # forward bank on x+ and adjoint bank, one
 KERNEL_SOURCES = ["common.hpp", "device_math.hpp", "kernels_trial.hpp", "foe_lib.hip"]   # kernels and their launch shapes
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "foe_trial_kernel_512x512_hbm_traffic.md")
 UNFUSED_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "foe_trial_kernel_unfused_512x512_hbm_traffic.md")
+TILE_SHAPES = ["32x32", "32x16", "32x8", "64x8"]   # foe_set_tile_config indices
 
 
 def log(msg):
@@ -467,12 +468,12 @@ def form_context(dev):
         p = foe.default_params(H, W, lambda1=pr.lam1, lambda2=pr.lam2, max_iters=300, looks=8)
         s = foe.Solver(p, bank, theta)
         f = torch.from_numpy(pr.f).to(dev)
-        cfg = s.autotune(f, reps=5)   # the tile shape for this size (32 x 16 fills more CUs on small images)
+        cfg = s.autotune(f, reps=5)   # the tile shape for this size (smaller tiles fill more CUs on small images)
         r = s.solve(f)
         t = _wall(lambda: s.solve(f), reps=5)
         n_it = r.summary["iters_done"]
         out[f"{W}x{H}"] = {"gpu_ms_per_solve": round(t * 1e3, 3), "gpu_mpix_it_s": round(H * W * n_it / t / 1e6, 1),
-                           "tile": "32x32" if cfg == 0 else "32x16",
+                           "tile": TILE_SHAPES[cfg],
                            "psnr_noisy": round(synth.psnr(pr.f, pr.clean), 4),
                            "psnr_gpu": round(synth.psnr(r.u.cpu().numpy(), pr.clean), 4),
                            "paper_gtx680_s_per_solve": paper_s[(H, W)]}
