@@ -193,3 +193,21 @@ def test_line_search_exhaustion_status():
     res = oracle.ipiano(p, f, bank, theta, 5, L0=1e-6)
     assert res.status == oracle.ELINESEARCH
     assert np.array_equal(res.x, np.log(f.astype(np.float64)))   # left at the last accepted iterate
+
+
+def test_nonfinite_status():
+    """A trial whose energy overflows (weights theta_i = 1e300: F sums 1e300 log(1 + y^2) over the image) ends
+    the run with ENONFINITE in the fixed-step mode, before any iterate is taken; under backtracking such a trial
+    is rejected like any other and the line search runs out."""
+    clean, f = _small_problem(16, 16, looks=1, seed=9)
+    bank = synth.dct_bank()
+    theta = np.full(len(bank), 1e300)
+    x0 = np.log(f.astype(np.float64))
+    p = oracle.Params(model=oracle.COMBINED, lam1=160.0, lam2=0.004, beta=0.8, step_mode=oracle.FIXED, alpha_fixed=1e-3)
+    res = oracle.ipiano(p, f, bank, theta, 5)
+    assert res.status == oracle.ENONFINITE
+    assert np.array_equal(res.x, x0)
+    pb = oracle.Params(model=oracle.COMBINED, lam1=160.0, lam2=0.004, beta=0.8, max_backtracks=3)
+    res = oracle.ipiano(pb, f, bank, theta, 5, L0=1.0)
+    assert res.status == oracle.ELINESEARCH
+    assert np.array_equal(res.x, x0)
