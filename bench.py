@@ -16,7 +16,10 @@ backtracking, output) on synthetic input resident in HBM.  Prints one JSON line:
   forms         time-to-PSNR of the batched, BF16 and warm-started forms against the plain FP32
                 solver on their own workloads (the wall time to reach the plain run's final PSNR
                 minus 0.01 dB, or 0.05 dB for BF16; the crossing iteration is found with a PSNR probe
-                and a separate run of exactly that many iterations is timed)
+                and a separate run of exactly that many iterations is timed), and time-to-energy (H
+                within 0.5 % of the plain final H) for the BF16 and warm-started forms; the warm start
+                also on 64 held-out images, the unfused gradient, the Lambert-W prox and the run-time
+                points of Sec. III-D
 """
 from __future__ import annotations
 
@@ -390,6 +393,16 @@ def form_warm(dev):
             "seconds_network": round(t_net, 5), "speedup": round(t_plain / t_warm, 3), **energy}
 
 
+def form_warm_eval(dev, n_images=64):
+    """The warm start on held-out 512 x 512 images (seeds disjoint from the network's training images), batched:
+    mean PSNR of network + 40 iterations (with the energy fallback) against the plain 300 iterations and
+    against 40 iterations from log f; the energy gap to the plain run and the fallback rate."""
+    from paper_1404_5344_amd import warmstart as ws
+    out = ws.report(n_images, workers=1, quiet=True)
+    out["workload"] = f"{n_images} held-out 512x512 images, L in {{1, 2, 4, 8}}, DCT bank"
+    return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in out.items()}
+
+
 def form_unfused(dev, steps=5):
     """The same 512 x 512 solve with the gradient split in two launches that exchange the 48 z planes
     through HBM (forward half writes them, adjoint half reads them), against the fused kernel."""
@@ -645,6 +658,7 @@ def main():
     if not args.no_forms:
         forms = {}
         for name, fn in (("batched", form_batched), ("bf16", form_bf16), ("warm_start", form_warm),
+                         ("warm_start_eval", form_warm_eval),
                          ("unfused", form_unfused), ("lambertw", form_lambertw), ("context", form_context)):
             t = time.perf_counter()
             log(f"bench: form {name}")

@@ -176,13 +176,14 @@ def held_out(n_images: int, workers: int = 8):
     return np.stack([r[0] for r in res]), np.stack([r[1] for r in res]), [r[2] for r in res]
 
 
-def report(n_images: int, path: str = WEIGHTS, iters_warm: int = 40, iters_plain: int = 300) -> dict:
+def report(n_images: int, path: str = WEIGHTS, iters_warm: int = 40, iters_plain: int = 300, workers: int = 8,
+           quiet: bool = False) -> dict:
     """Held-out evaluation: PSNR and energy of the warm start (with fallback) against the plain
-    run and against the same iteration count from log f."""
+    run and against the same iteration count from log f (printed as one JSON line unless quiet)."""
     import json
     import synth
     import torch
-    f_np, clean, looks = held_out(n_images)
+    f_np, clean, looks = held_out(n_images, workers)
     f = torch.from_numpy(f_np).to("cuda:0")
     net = load(path)
     u_plain, u_short, u_warm, rec = evaluate(net, f, looks, synth.dct_bank(), synth.theta_weights(5), iters_warm,
@@ -197,7 +198,8 @@ def report(n_images: int, path: str = WEIGHTS, iters_warm: int = 40, iters_plain
                energy_gap_mean=float(gap.mean()), energy_gap_max=float(gap.max()),
                fallback_rate=float(np.mean([r["fallback"] for r in rec])))
     net.close()
-    print(json.dumps(out), flush=True)
+    if not quiet:
+        print(json.dumps(out), flush=True)
     return out
 
 
