@@ -100,19 +100,11 @@ struct ZLines {
 };
 
 // The mirror terms of FB consecutive positions along an edge for one filter: v_i(d) = sum_{r <= 2 - d}
-// <K_{d+r}, Z_r[i .. i + 6]> with Z_r[s] = zl(r, s) (s = 0 .. FB + 5) and K_m[t] = kb[m KL + t KT],
-// added to out[(i R + d) NC] (each partial has one writer per chunk).  The z lines slide through
-// registers, the tap lines are loaded once.
-template <int FB, int NC, int KT, int KL, class ZL>
-__device__ __forceinline__ void fold_block(ZL zl, const float* kb, float* out) {
-  float Z[R][FB + KS - 1], K[R][KS];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-#pragma unroll
-    for (int s = 0; s < FB + KS - 1; ++s) Z[r][s] = zl(r, s);
-#pragma unroll
-    for (int t = 0; t < KS; ++t) K[r][t] = kb[r * KL + t * KT];
-  }
+// <K_{d+r}, Z_r[i .. i + 6]> with Z_r[s] the z line at distance r from the edge (s = 0 .. FB + 5) and K_m the
+// tap line 4 + m (low edge) or 2 - m (high edge), added to out[(i R + d) NC] (each partial has one writer per
+// chunk).
+template <int FB, int NC>
+__device__ __forceinline__ void fold_sums(const float (&Z)[R][FB + KS - 1], const float (&K)[R][KS], float* out) {
 #pragma unroll
   for (int i = 0; i < FB; ++i) {
     float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
@@ -129,6 +121,93 @@ __device__ __forceinline__ void fold_block(ZL zl, const float* kb, float* out) {
     out[(i * R + 1) * NC] += v1;
     out[(i * R + 2) * NC] += v2;
   }
+}
+
+// fold_sums with Z_r[s] = zl(r, s) and K_m[t] = kb[m KL + t KT], read one value at a time.
+template <int FB, int NC, int KT, int KL, class ZL>
+__device__ __forceinline__ void fold_block(ZL zl, const float* kb, float* out) {
+  float Z[R][FB + KS - 1], K[R][KS];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int s = 0; s < FB + KS - 1; ++s) Z[r][s] = zl(r, s);
+#pragma unroll
+    for (int t = 0; t < KS; ++t) K[r][t] = kb[r * KL + t * KT];
+  }
+  fold_sums<FB, NC>(Z, K, out);
+}
+
+// fold_sums on a y edge of the FP32 planes.  zl: the edge line (plane row) at column p0, from an 8-byte boundary
+// (even plane and row strides, even p0); the lines run away from the edge by zs = +ZW (low edge) or -ZW (high).
+// ka_j: the filter's adjoint taps from a 16-byte boundary; the tap lines 4..6 (low) or 2..0 (high) are the 21
+// consecutive taps 28..48 or 0..20.  Pairs and quads of consecutive values are read together.
+template <int FB, int NC, bool LO>
+__device__ __forceinline__ void fold_block_y(const float* zl, int zs, const float* ka_j, float* out) {
+  static_assert((FB + KS - 1) % 2 == 0, "the z lines read as pairs");
+  float Z[R][FB + KS - 1], K[R][KS], kb[24];
+  const float4* k4 = reinterpret_cast<const float4*>(ka_j + (LO ? (R + 1) * KS : 0));
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const float4 v = k4[q];
+    kb[4 * q] = v.x; kb[4 * q + 1] = v.y; kb[4 * q + 2] = v.z; kb[4 * q + 3] = v.w;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int t = 0; t < KS; ++t) K[r][t] = kb[(LO ? r : R - 1 - r) * KS + t];
+    const float* zr = zl + r * zs;
+#pragma unroll
+    for (int s = 0; s < FB + KS - 1; s += 2) {
+      const float2 v = *reinterpret_cast<const float2*>(zr + s);
+      Z[r][s] = v.x;
+      Z[r][s + 1] = v.y;
+    }
+  }
+  fold_sums<FB, NC>(Z, K, out);
+}
+
+// fold_sums on an x edge of the FP32 planes.  zl: row p0 of the plane (an even float offset), zcol: the plane
+// column of the edge line (R on the low edge), zw: the row stride (even); the lines are the columns zcol, zcol +
+// 1, zcol + 2 (low) or zcol, zcol - 1, zcol - 2 (high), each three taken as one pair and one single value.  The
+// tap lines are the columns 4..6 (low) or 2..0 (high) of every tap row of ka_j (16-byte aligned).
+template <int FB, int NC, bool LO>
+__device__ __forceinline__ void fold_block_x(const float* zl, int zw, int zcol, const float* ka_j, float* out) {
+  float Z[R][FB + KS - 1], K[R][KS];
+#pragma unroll
+  for (int t = 0; t < KS; ++t) {
+    // low: taps 7t + 4 + r; high: taps 7t + 2 - r.  b: the lowest of the three (its parity is known once t is)
+    const int b = KS * t + (LO ? R + 1 : 0);
+    if (b % 2 == 0) {
+      const float2 v = *reinterpret_cast<const float2*>(ka_j + b);
+      const float w = ka_j[b + 2];
+      if (LO) { K[0][t] = v.x; K[1][t] = v.y; K[2][t] = w; }
+      else { K[2][t] = v.x; K[1][t] = v.y; K[0][t] = w; }
+    } else {
+      const float w = ka_j[b];
+      const float2 v = *reinterpret_cast<const float2*>(ka_j + b + 1);
+      if (LO) { K[0][t] = w; K[1][t] = v.x; K[2][t] = v.y; }
+      else { K[2][t] = w; K[1][t] = v.x; K[0][t] = v.y; }
+    }
+  }
+  const int c0 = LO ? zcol : zcol - (R - 1);   // the lowest of the three columns
+  if (c0 % 2 == 0) {
+#pragma unroll
+    for (int s = 0; s < FB + KS - 1; ++s) {
+      const float2 v = *reinterpret_cast<const float2*>(zl + s * zw + c0);
+      const float w = zl[s * zw + c0 + 2];
+      if (LO) { Z[0][s] = v.x; Z[1][s] = v.y; Z[2][s] = w; }
+      else { Z[2][s] = v.x; Z[1][s] = v.y; Z[0][s] = w; }
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < FB + KS - 1; ++s) {
+      const float w = zl[s * zw + c0];
+      const float2 v = *reinterpret_cast<const float2*>(zl + s * zw + c0 + 1);
+      if (LO) { Z[0][s] = w; Z[1][s] = v.x; Z[2][s] = v.y; }
+      else { Z[2][s] = w; Z[1][s] = v.x; Z[0][s] = v.y; }
+    }
+  }
+  fold_sums<FB, NC>(Z, K, out);
 }
 
 // Operands of the matrix-core forward bank that stay in registers for one chunk of 16 filters.
@@ -1049,11 +1128,9 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
               fold_block<FB, NC, 1, -KS>(ZLines<1, -ZS::W, true>{zl}, ka_s + j * KAP + (R - 1) * KS, out);
           } else {
             if (lo)
-              fold_block<FB, NC, 1, KS>(ZLines<1, ZW>{zp + j * PLANE + zrow * ZW + p0}, ka_s + j * KAP + (R + 1) * KS,
-                                        out);
+              fold_block_y<FB, NC, true>(zp + j * PLANE + zrow * ZW + p0, ZW, ka_s + j * KAP, out);
             else
-              fold_block<FB, NC, 1, -KS>(ZLines<1, -ZW>{zp + j * PLANE + zrow * ZW + p0},
-                                         ka_s + j * KAP + (R - 1) * KS, out);
+              fold_block_y<FB, NC, false>(zp + j * PLANE + zrow * ZW + p0, -ZW, ka_s + j * KAP, out);
           }
         } else if (it < f_c0) {
           // x edge block, tile rows p0 .. p0 + FB - 1: z lines are plane columns, taps run down tap columns
@@ -1073,9 +1150,9 @@ __global__ __launch_bounds__(NT) void foe_trial_kernel(FusedArgs a) {
               fold_block<FB, NC, KS, -1>(ZLines<ZS::W, -1, true>{zl}, ka_s + j * KAP + R - 1, out);
           } else {
             if (lo)
-              fold_block<FB, NC, KS, 1>(ZLines<ZW, 1>{zp + j * PLANE + p0 * ZW + zcol}, ka_s + j * KAP + R + 1, out);
+              fold_block_x<FB, NC, true>(zp + j * PLANE + p0 * ZW, ZW, zcol, ka_s + j * KAP, out);
             else
-              fold_block<FB, NC, KS, -1>(ZLines<ZW, -1>{zp + j * PLANE + p0 * ZW + zcol}, ka_s + j * KAP + R - 1, out);
+              fold_block_x<FB, NC, false>(zp + j * PLANE + p0 * ZW, ZW, zcol, ka_s + j * KAP, out);
           }
         } else {
           // a corner row (-1 - i or H + i) of an x edge: window rows outside the plane are off the image

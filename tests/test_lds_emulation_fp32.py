@@ -176,6 +176,9 @@ def emulate_tile(z_img, ka, H, W, x0, y0, TW, TH, fwd):
                 out0 = ((0 if lo else TW) + p0) * R * NC + j
                 zrow = R if lo else H - 1 - y0 + R
                 base = j * PLANE + zrow * ZW + p0
+                # fold_block_y: the z lines as float2 pairs, the 24 taps from (R + 1) KS or 0 as float4 quads
+                assert base % 2 == 0 and ZW % 2 == 0 and (j * KAP + ((R + 1) * KS if lo else 0)) % 4 == 0
+                assert j * KAP + ((R + 1) * KS if lo else 0) + 24 <= (j + 1) * KAP
                 if lo:
                     fold_block(zp, base, 1, ZW, ka_s, j * KAP + (R + 1) * KS, 1, KS, fpart, out0, writes)
                 else:
@@ -187,6 +190,8 @@ def emulate_tile(z_img, ka, H, W, x0, y0, TW, TH, fwd):
                 out0 = (2 * TW + (0 if lo else NPX) + p0) * R * NC + j
                 zcol = R if lo else W - 1 - x0 + R
                 base = j * PLANE + p0 * ZW + zcol
+                # fold_block_x: each three columns as a float2 pair from an even offset and a single value
+                assert (j * PLANE + p0 * ZW) % 2 == 0 and ZW % 2 == 0 and (j * KAP) % 2 == 0
                 if lo:
                     fold_block(zp, base, ZW, 1, ka_s, j * KAP + R + 1, KS, 1, fpart, out0, writes)
                 else:
