@@ -33,9 +33,6 @@ __host__ constexpr int total_params() {
   return n;
 }
 
-// out[n][co][p] = act(bias[co] + sum_ci sum_t wt[ci][t][co] in[n][ci][p + off_t]) * (mask[n][co][p] > 0),
-// act = ReLU when relu != 0; bias and mask nullable; zero padding.  wt (CI 9 CO values) is staged in
-// LDS and read as block-wide broadcasts.
 // The tile of block b of a 1-D grid of 8 * per blocks over ntiles tiles (images, tile rows, tile columns,
 // row-major): blocks are dealt to the 8 XCDs in turn, so XCD b % 8 takes the consecutive tiles
 // (b % 8) per .. (b % 8 + 1) per - 1, and tiles that share halo lines share one L2.  False when the
@@ -52,6 +49,10 @@ __device__ __forceinline__ bool xcd_tile(int H, int W, int n_img, int* x0, int* 
   return true;
 }
 
+// out[n][co][p] = act(bias[co] + sum_ci sum_t wt[ci][t][co] in[n][ci][p + off_t]) * (mask[n][co][p] > 0),
+// act = ReLU when relu != 0; bias and mask nullable; zero padding.  wt (CI 9 CO values) is staged in
+// LDS and read as block-wide broadcasts.
+// One 16 x 16 tile per block (xcd_tile).
 template <int CI, int CO, int CICH>
 __global__ __launch_bounds__(256) void conv3_kernel(const float* __restrict__ in, const float* __restrict__ wt,
                                                     const float* __restrict__ bias, float* __restrict__ out,
