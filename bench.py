@@ -18,7 +18,7 @@ backtracking, output) on synthetic input resident in HBM.  Prints one JSON line:
                 minus 0.01 dB, or 0.05 dB for BF16; the crossing iteration is found with a PSNR probe
                 and a separate run of exactly that many iterations is timed), and time-to-energy (H
                 within 0.5 % of the plain final H) for the BF16 and warm-started forms; the warm start
-                also on 64 held-out images, the unfused gradient, the Lambert-W prox and the run-time
+                also on the 256 held-out images, the unfused gradient, the Lambert-W prox and the run-time
                 points of Sec. III-D
 """
 from __future__ import annotations
@@ -393,10 +393,10 @@ def form_warm(dev):
             "seconds_network": round(t_net, 5), "speedup": round(t_plain / t_warm, 3), **energy}
 
 
-def form_warm_eval(dev, n_images=64):
-    """The warm start on held-out 512 x 512 images (seeds disjoint from the network's training images), batched:
-    mean PSNR of network + 40 iterations (with the energy fallback) against the plain 300 iterations and
-    against 40 iterations from log f; the energy gap to the plain run and the fallback rate."""
+def form_warm_eval(dev, n_images=256):
+    """The warm start on the 256 held-out 512 x 512 evaluation images (seeds disjoint from the network's training
+    images), batched: mean PSNR of network + 40 iterations (with the energy fallback) against the plain 300
+    iterations and against 40 iterations from log f; the energy gap to the plain run and the fallback rate."""
     from paper_1404_5344_amd import warmstart as ws
     out = ws.report(n_images, workers=1, quiet=True)
     out["workload"] = f"{n_images} held-out 512x512 images, L in {{1, 2, 4, 8}}, DCT bank"
