@@ -204,7 +204,8 @@ def _wall_prepped(prep, run, reps=3):
 
 
 def form_bf16(dev):
-    """BF16 filter bank on the first 2048 x 2048 SAR-like tile against the FP32 solve."""
+    """BF16 filter bank against the FP32 solve: time-to-PSNR and time-to-energy on the first 2048 x 2048 SAR-like
+    tile, then the four tiles in one batch in each precision (per-tile PSNR, batch throughput)."""
     import torch
     import paper_1404_5344_amd as foe
     import synth
@@ -246,6 +247,24 @@ def form_bf16(dev):
     out["energy_speedup"] = round(out["energy_seconds_fp32"] / out["energy_seconds_bf16"], 3)
     for s in solvers.values():
         s.close()
+    # the whole workload, the four tiles in one batch, in each precision: per-tile final PSNR and the
+    # throughput of the batch
+    tiles = [pr] + [synth.config4(i) for i in (1, 2, 3)]
+    n = 2048 * 2048
+    fb = torch.cat([torch.from_numpy(q.f).reshape(-1) for q in tiles]).to(dev)
+    four = {"workload": "4 x 2048x2048 SAR-like tiles in one batch, L=1, 300 iterations"}
+    for name, kw in (("fp32", {}), ("bf16", dict(precision=1))):
+        b = foe.BatchSolver(foe.default_params(0, 0, max_iters=300, **kw), [(2048, 2048)] * 4, [q.looks for q in tiles],
+                            bank, theta, lambda1=[q.lam1 for q in tiles], lambda2=[q.lam2 for q in tiles])
+        u = b.solve(fb)[0]
+        four[f"psnr_{name}"] = [round(synth.psnr(u[i * n:(i + 1) * n].reshape(2048, 2048).cpu().numpy(), q.clean, q.peak), 4)
+                                for i, q in enumerate(tiles)]
+        t = _wall(lambda: b.solve(fb), reps=2)
+        four[f"mpix_it_s_{name}"] = round(4 * n * 300 / t / 1e6, 1)
+        b.close()
+    four["max_abs_psnr_diff_db"] = round(max(abs(a - c) for a, c in zip(four["psnr_fp32"], four["psnr_bf16"])), 4)
+    four["speedup"] = round(four["mpix_it_s_bf16"] / four["mpix_it_s_fp32"], 3)
+    out["four_tiles"] = four
     return out
 
 
